@@ -1,0 +1,198 @@
+"""CPU oracle for the Hamming kNN-graph builder -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, the smoke check in ``__graft_entry__`` and the CPU-baseline leg
+of ``bench.py`` may import this package. The product path (the GPU library and
+its binding) never imports, links or runs anything here, and nothing here uses
+the GPU library: the two share no code. Inputs come from the seeded generators
+in ``paper_2102_04656_amd.datagen``, which hold none of the method's arithmetic.
+
+Contents
+  * ``knn_tiny``          -- pure-Python per-bit brute force with a full sort
+                             (tiny inputs only); the plain definition.
+  * ``knn_rows``          -- the same definition in plain C (``hamming_oracle.c``),
+                             for rows sampled from large inputs.
+  * ``knn_blocks``        -- per-column-block lists (the partition search of the
+                             reduce step, Sec. 3.2) by the same C routine.
+  * ``merge_lists``       -- top-K of the deduplicated union of lists (the
+                             merge-sort of the second reduce, Sec. 3.2 / 3.3).
+  * ``knn_sharded_rows``  -- the definition applied per shard, local indices.
+  * ``pair_distances``    -- Hamming distance of explicit pairs.
+Floating-point parts of the learned binariser live in ``oracle.learned``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+NO_IDX = 0xFFFFFFFF
+NO_DIST = 0xFFFF
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hamming_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (OpenMP). Portable x86-64 flags only: the
+    library may run on another host than the one that built it."""
+    if not force and os.path.exists(_LIB):
+        return _LIB
+    tmp = _LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-mpopcnt", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+           "-Wall", "-Wextra", "-o", tmp, _SRC]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build()
+            lib = ctypes.CDLL(_LIB)
+            u32, u64, p = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p
+            lib.oracle_knn_rows.argtypes = [p, u32, u32, u32, u32, u32, p, u32, p, p]
+            lib.oracle_knn_rows.restype = ctypes.c_int
+            lib.oracle_pair_distances.argtypes = [p, u32, p, p, u64, p]
+            lib.oracle_pair_distances.restype = None
+            lib.oracle_threads.restype = ctypes.c_int
+            lib.oracle_set_threads.argtypes = [ctypes.c_int]
+            _lib = lib
+    return _lib
+
+
+def threads() -> int:
+    return int(_load().oracle_threads())
+
+
+def set_threads(t: int) -> None:
+    _load().oracle_set_threads(int(t))
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+# --------------------------------------------------------------------------
+# Pure-Python definition (tiny inputs)
+# --------------------------------------------------------------------------
+
+def _bit(codes, i, j):
+    """Bit j of code i: word j // 64, position j % 64 (little-endian)."""
+    return (int(codes[i][j // 64]) >> (j % 64)) & 1
+
+
+def hamming_tiny(codes, i, j) -> int:
+    """Count of bit positions in which codes i and j differ (per-bit loop)."""
+    bits = 64 * len(codes[0])
+    return sum(1 for b in range(bits) if _bit(codes, i, b) != _bit(codes, j, b))
+
+
+def knn_tiny(codes, K: int):
+    """Row i = first K of sorted [(ham(i, j), j) for j != i], sentinel-padded.
+
+    Plain definition with Python's sort; only for n of a few hundred at most.
+    """
+    codes = [[int(w) for w in row] for row in np.asarray(codes, dtype=np.uint64)]
+    n = len(codes)
+    idx = np.full((n, K), NO_IDX, dtype=np.uint32)
+    dist = np.full((n, K), NO_DIST, dtype=np.uint16)
+    for i in range(n):
+        keys = sorted((hamming_tiny(codes, i, j), j) for j in range(n) if j != i)
+        for r, (d, j) in enumerate(keys[:K]):
+            idx[i, r] = j
+            dist[i, r] = d
+    return idx, dist
+
+
+# --------------------------------------------------------------------------
+# Plain C brute force
+# --------------------------------------------------------------------------
+
+def knn_rows(codes: np.ndarray, K: int, rows=None, cols=None):
+    """Exact kNN rows of ``codes`` (``[n][W]`` uint64) against columns
+    ``cols = (c0, c1)`` (default all), for ``rows`` (default all)."""
+    codes = np.ascontiguousarray(codes, dtype=np.uint64)
+    n, words = codes.shape
+    c0, c1 = (0, n) if cols is None else (int(cols[0]), int(cols[1]))
+    if rows is None:
+        nrows, rptr, keep = n, None, None
+    else:
+        keep = np.ascontiguousarray(rows, dtype=np.uint32)
+        nrows, rptr = keep.size, _ptr(keep)
+    idx = np.empty((nrows, K), dtype=np.uint32)
+    dist = np.empty((nrows, K), dtype=np.uint16)
+    if nrows:
+        rc = _load().oracle_knn_rows(_ptr(codes), n, words, K, c0, c1, rptr, nrows,
+                                     _ptr(idx), _ptr(dist))
+        if rc != 0:
+            raise RuntimeError("oracle_knn_rows failed")
+    return idx, dist
+
+
+def knn_blocks(codes: np.ndarray, K: int, col_block: int, rows=None):
+    """Per-column-block lists ``[L][nrows][K]`` (each block searched alone)."""
+    n = codes.shape[0]
+    bounds = [(c, min(n, c + col_block)) for c in range(0, n, col_block)]
+    parts = [knn_rows(codes, K, rows=rows, cols=b) for b in bounds]
+    return (np.stack([p[0] for p in parts]), np.stack([p[1] for p in parts]))
+
+
+def pair_distances(codes: np.ndarray, a, b) -> np.ndarray:
+    codes = np.ascontiguousarray(codes, dtype=np.uint64)
+    a = np.ascontiguousarray(a, dtype=np.uint32)
+    b = np.ascontiguousarray(b, dtype=np.uint32)
+    out = np.empty(a.size, dtype=np.uint16)
+    if a.size:
+        _load().oracle_pair_distances(_ptr(codes), codes.shape[1], _ptr(a), _ptr(b),
+                                      a.size, _ptr(out))
+    return out
+
+
+# --------------------------------------------------------------------------
+# Merge of neighbour lists (second reduce: merge all lists of one label and
+# sort out the final kNN)
+# --------------------------------------------------------------------------
+
+def merge_lists(in_idx: np.ndarray, in_dist: np.ndarray, K: int):
+    """``in_idx/in_dist [L][n][K_in]`` -> top-K ``[n][K]`` of the union.
+
+    Per row: drop sentinel entries (idx == 0xFFFFFFFF), remove repeated
+    (dist, idx) pairs, sort ascending by (dist, idx), keep K, pad with
+    sentinels. Lists that name one index with two different distances are
+    outside the contract (distances are a function of the pair).
+    """
+    in_idx = np.asarray(in_idx, dtype=np.uint32)
+    in_dist = np.asarray(in_dist, dtype=np.uint16)
+    L, n, kin = in_idx.shape
+    out_idx = np.full((n, K), NO_IDX, dtype=np.uint32)
+    out_dist = np.full((n, K), NO_DIST, dtype=np.uint16)
+    for r in range(n):
+        pairs = set()
+        for l in range(L):
+            for t in range(kin):
+                j = int(in_idx[l, r, t])
+                if j != NO_IDX:
+                    pairs.add((int(in_dist[l, r, t]), j))
+        for k, (d, j) in enumerate(sorted(pairs)[:K]):
+            out_idx[r, k] = j
+            out_dist[r, k] = d
+    return out_idx, out_dist
+
+
+# --------------------------------------------------------------------------
+# Many independent partitions (shards), indices local to the shard
+# --------------------------------------------------------------------------
+
+def knn_sharded_rows(codes: np.ndarray, offsets, K: int, shard: int, rows=None):
+    """kNN rows of one shard; ``rows`` are shard-local row ids."""
+    lo, hi = int(offsets[shard]), int(offsets[shard + 1])
+    return knn_rows(codes[lo:hi], K, rows=rows)

@@ -1,0 +1,75 @@
+"""Readers for the hand-derived fixtures under tests/golden/."""
+import os
+
+import numpy as np
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _lines(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                yield line
+
+
+def cube3():
+    """-> (layouts, expected_idx [8][7], expected_dist [8][7]).
+
+    Each layout is (bits, positions, background)."""
+    layouts, rows = [], {}
+    for line in _lines("cube3_knn.txt"):
+        if line.startswith("layout"):
+            kv = dict(tok.split("=") for tok in line.split()[1:])
+            layouts.append((int(kv["bits"]), [int(p) for p in kv["positions"].split(",")],
+                            int(kv["background"])))
+        elif line.startswith("row"):
+            head, body = line.split(":", 1)
+            idx_s, dist_s = body.split("|")
+            rows[int(head.split()[1])] = ([int(t) for t in idx_s.split()],
+                                          [int(t) for t in dist_s.split()])
+    idx = np.array([rows[r][0] for r in range(8)], dtype=np.uint32)
+    dist = np.array([rows[r][1] for r in range(8)], dtype=np.uint16)
+    return layouts, idx, dist
+
+
+def cube3_codes(bits, positions, background):
+    """Codes of the 8 vertices in a given layout (written bit by bit)."""
+    words = bits // 64
+    codes = np.zeros((8, words), dtype=np.uint64)
+    for i in range(8):
+        for b in range(bits):
+            val = background
+            if b in positions:
+                val = (i >> positions.index(b)) & 1
+            if val:
+                codes[i, b // 64] |= np.uint64(1) << np.uint64(b % 64)
+    return codes
+
+
+def merge_small():
+    """-> (K, in_idx [L][n][K_in], in_dist, out_idx [n][K], out_dist)."""
+    ins, outs, K = {}, {}, None
+    for line in _lines("merge_small.txt"):
+        if line.startswith("K "):
+            K = int(line.split()[1])
+            continue
+        head, body = line.split(":", 1)
+        pairs = [tuple(int(v) for v in tok.split(",")) for tok in body.split()]
+        parts = head.split()
+        if parts[0] == "in":
+            ins[(int(parts[1]), int(parts[2]))] = pairs
+        else:
+            outs[int(parts[1])] = pairs
+    n = 1 + max(r for r, _ in ins)
+    L = 1 + max(l for _, l in ins)
+    kin = len(next(iter(ins.values())))
+    in_idx = np.zeros((L, n, kin), dtype=np.uint32)
+    in_dist = np.zeros((L, n, kin), dtype=np.uint16)
+    for (r, l), pairs in ins.items():
+        in_dist[l, r] = [p[0] for p in pairs]
+        in_idx[l, r] = [p[1] for p in pairs]
+    out_idx = np.array([[p[1] for p in outs[r]] for r in range(n)], dtype=np.uint32)
+    out_dist = np.array([[p[0] for p in outs[r]] for r in range(n)], dtype=np.uint16)
+    return K, in_idx, in_dist, out_idx, out_dist
