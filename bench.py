@@ -1,0 +1,250 @@
+#!/usr/bin/env python3
+"""Benchmark of the exact Hamming kNN-graph build on one MI355X.
+
+One step = one ``bdg_build_knn_ex`` call over the whole workload: every
+(row block x column block) distance tile with its fused top-K, the merge of
+the per-column-block lists, and the output rows. Codes are resident in HBM
+before the timed region starts.
+
+Default workload: 1,000,000 codes of 256 bits from 1,000 random centres with
+bit-flip probability 0.2, exact K = 64 graph, built in 131072 x 131072 blocks
+with merged per-block lists.
+
+Prints ONE JSON line on stdout. ``value`` = n (n - 1) / seconds per step
+(pair distances per second). ``roofline`` is for the dominant kernel (the
+distance tile), timed live with HIP events recorded around every tile launch on
+the launch stream. ``cpu_baseline`` times the CPU oracle on a bounded seeded
+row sample of the same workload.
+
+    python bench.py [--steps 5] [--warmup 2] [--path auto|mfma|popc]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK_INT8_TOPS = 5000.0           # dense int8 matrix, TOP/s
+CU, LANES, CLOCK = 256, 64, 2.4e9
+PEAK_VALU_TOPS = CU * LANES * CLOCK / 1e12  # 32-bit integer vector ops, TOP/s (derived)
+METRIC = "Hamming kNN-graph build pair-dist/s + % peak; recall@K learned vs plain codes"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class HipEvents:
+    """hipEvent_t handles created through the HIP runtime's C API."""
+
+    def __init__(self, count: int):
+        self.rt = ctypes.CDLL("libamdhip64.so")
+        self.rt.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.rt.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
+                                                ctypes.c_void_p]
+        self.rt.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.handles = (ctypes.c_void_p * count)()
+        for i in range(count):
+            h = ctypes.c_void_p()
+            if self.rt.hipEventCreate(ctypes.byref(h)) != 0:
+                raise RuntimeError("hipEventCreate failed")
+            self.handles[i] = h.value
+
+    def slice_ptr(self, start: int) -> int:
+        return ctypes.addressof(self.handles) + start * ctypes.sizeof(ctypes.c_void_p)
+
+    def elapsed_ms(self, a: int, b: int) -> float:
+        ms = ctypes.c_float()
+        if self.rt.hipEventElapsedTime(ctypes.byref(ms), self.handles[a], self.handles[b]) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return ms.value
+
+    def close(self):
+        for h in self.handles:
+            self.rt.hipEventDestroy(h)
+
+
+def run_path(codes_dev, n, bits, K, path, row_block, col_block, steps, warmup):
+    """Time `steps` full builds; returns (ms/step, tile kernel stats, outputs)."""
+    import torch
+    from paper_2102_04656_amd import bdg
+
+    nrb = (n + row_block - 1) // row_block
+    idx = torch.empty((n, K), dtype=torch.int32, device="cuda")
+    dist = torch.empty((n, K), dtype=torch.int16, device="cuda")
+    stream = torch.cuda.current_stream()
+    ev = HipEvents(2 * nrb * steps)
+    # workspace allocated once, outside the timed region
+    o = bdg.make_opts(path=path, row_block=row_block, col_block=col_block)
+    ws_bytes = bdg.bdg_build_knn_workspace_size(n, bits, K, o)
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device="cuda")
+
+    def step(s):
+        op = bdg.make_opts(path=path, row_block=row_block, col_block=col_block,
+                           workspace=ws.data_ptr(), workspace_bytes=ws_bytes)
+        if s is not None:
+            op.n_tile_events = 2 * nrb
+            op.tile_events = ev.slice_ptr(2 * nrb * s)
+        st = bdg.bdg_build_knn_ex(codes_dev, n, bits, K, idx, dist, op, stream)
+        if st != 0:
+            raise RuntimeError(f"bdg_build_knn_ex failed: {st} {bdg.last_error()}")
+
+    for _ in range(warmup):
+        step(None)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        step(s)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / steps
+    durs, pairs = [], []
+    for s in range(steps):
+        for rb in range(nrb):
+            e = 2 * nrb * s + 2 * rb
+            durs.append(ev.elapsed_ms(e, e + 1))
+            rows = min(row_block, n - rb * row_block)
+            pairs.append(rows * (n - 1))
+    ev.close()
+    return ms_step, dict(launches=len(durs), avg_ms=float(np.mean(durs)),
+                         pairs_per_launch=float(np.mean(pairs)),
+                         total_ms=float(np.sum(durs))), (idx, dist)
+
+
+def cpu_baseline(codes, K, gpu_out, target_s):
+    """Time the CPU oracle on a bounded seeded row sample of the workload."""
+    import oracle
+    from paper_2102_04656_amd import bdg
+    n = codes.shape[0]
+    g = np.random.default_rng(2021)
+    calib = max(32, 2 * oracle.threads())
+    rows = np.sort(g.choice(n, size=calib, replace=False)).astype(np.uint32)
+    t0 = time.perf_counter()
+    oracle.knn_rows(codes, K, rows=rows)
+    t_cal = time.perf_counter() - t0
+    R = int(min(n, max(calib, calib * target_s / max(t_cal, 1e-3))))
+    rows = np.sort(g.choice(n, size=R, replace=False)).astype(np.uint32)
+    t0 = time.perf_counter()
+    oi, od = oracle.knn_rows(codes, K, rows=rows)
+    t = time.perf_counter() - t0
+    gi, gd = bdg.to_numpy_graph(*gpu_out)
+    parity = bool(np.array_equal(gi[rows], oi) and np.array_equal(gd[rows], od))
+    return dict(value=R * (n - 1) / t, unit="pair-dist/s", cores=oracle.threads(),
+                kind="oracle", seconds=t,
+                sample=f"{R} seeded rows x all {n} columns of the same workload "
+                       f"(exact K={K} rows by the C oracle)",
+                parity_on_sample=parity)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__,
+                                 formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--path", choices=["auto", "mfma", "popc"], default="auto")
+    ap.add_argument("--workload", default="clustered-1m-256b-k64")
+    ap.add_argument("--other-path", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time the other distance path (reported, not the value)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the graph build of one partition runs on a single "
+              "MI355X, and multi-GPU runs are not part of this library; use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2102_04656_amd import bdg, datagen
+    bdg.lib()
+    w = datagen.WORKLOADS[args.workload]
+    n, bits, K = w["n"], w["bits"], w["K"]
+    row_block, col_block = w.get("row_block", 131072), w.get("col_block", 131072)
+    log(f"[bench] generating {args.workload}: n={n} bits={bits} K={K}")
+    t0 = time.perf_counter()
+    codes = datagen.clustered_codes(n, bits, w["n_centres"], w["p"], w["seed"])
+    log(f"[bench] generated in {time.perf_counter() - t0:.1f}s")
+    codes_dev = torch.from_numpy(codes.view(np.int64)).cuda()
+    torch.cuda.synchronize()
+
+    paths = {"mfma": bdg.PATH_MFMA, "popc": bdg.PATH_POPC}
+    main_path = "mfma" if args.path == "auto" else args.path
+    runs = {}
+    order = [main_path] + ([p for p in paths if p != main_path] if args.other_path else [])
+    outs = None
+    for name in order:
+        log(f"[bench] timing path {name}: {args.steps} steps after {args.warmup} warmup")
+        ms, kern, out = run_path(codes_dev, n, bits, K, paths[name], row_block, col_block,
+                                 args.steps, args.warmup)
+        runs[name] = dict(ms_per_step=ms, kernel=kern)
+        if name == main_path:
+            outs = out
+        else:
+            del out
+        log(f"[bench] {name}: {ms:.2f} ms/step; tile kernel avg {kern['avg_ms']:.3f} ms "
+            f"x {kern['launches'] // args.steps} launches/step")
+
+    pairs = n * (n - 1)
+    ms = runs[main_path]["ms_per_step"]
+    kern = runs[main_path]["kernel"]
+    if main_path == "mfma":
+        ops_pair, peak, bound = 2 * bits, PEAK_INT8_TOPS, "mfma"
+    else:
+        ops_pair, peak, bound = 2 * bits // 32, PEAK_VALU_TOPS, "alu"
+    achieved = kern["pairs_per_launch"] * ops_pair / (kern["avg_ms"] * 1e-3) / 1e12
+    result = {
+        "metric": METRIC,
+        "value": pairs / (ms * 1e-3),
+        "unit": "pair-dist/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i8" if main_path == "mfma" else "u32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "bits": bits, "K": K,
+                   "row_block": row_block, "col_block": col_block, "path": main_path,
+                   "centres": w["n_centres"], "flip_p": w["p"], "seed": w["seed"]},
+        "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": f"knn_{main_path}_kernel",
+                     "kernel_avg_ms": kern["avg_ms"],
+                     "ops_per_pair": ops_pair,
+                     "pairs_per_launch": kern["pairs_per_launch"]},
+    }
+    for name, r in runs.items():
+        if name == main_path:
+            continue
+        if name == "mfma":
+            o2, p2 = 2 * bits, PEAK_INT8_TOPS
+        else:
+            o2, p2 = 2 * bits // 32, PEAK_VALU_TOPS
+        a2 = r["kernel"]["pairs_per_launch"] * o2 / (r["kernel"]["avg_ms"] * 1e-3) / 1e12
+        result[f"{name}_path"] = {"value": pairs / (r["ms_per_step"] * 1e-3),
+                                  "ms_per_step": r["ms_per_step"],
+                                  "kernel_avg_ms": r["kernel"]["avg_ms"],
+                                  "achieved": a2, "peak": p2, "frac": a2 / p2}
+    if not args.no_cpu_baseline:
+        log(f"[bench] CPU oracle baseline (~{args.cpu_seconds:.0f}s sample)")
+        result["cpu_baseline"] = cpu_baseline(codes, K, outs, args.cpu_seconds)
+        log(f"[bench] cpu baseline: {result['cpu_baseline']['value']:.3e} pair-dist/s on "
+            f"{result['cpu_baseline']['cores']} threads")
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,140 @@
+/*
+ * bdg.h -- C ABI of the MI355X (gfx950) exact Hamming kNN-graph builder.
+ *
+ * The library builds the k-nearest-neighbour graph of a set of binary codes
+ * under Hamming distance, the offline graph of Binary Distributed Graph
+ * (Sec. 3). Codes are the binary representation of Sec. 3.1; the graph of one
+ * partition is what the first reduce of the single-pass divide-and-conquer
+ * computes by exhaustive search (Sec. 3.2), and the merge of neighbour lists is
+ * the second reduce's merge-sort (Sec. 3.2, Sec. 3.3).
+ *
+ * Conventions for every entry point
+ *   - Pointers to codes, inputs (in_...) and outputs (out_...) are DEVICE
+ *     pointers (from hipMalloc or any device allocation, such as the data
+ *     pointer of a torch tensor), owned by the caller. The library never frees
+ *     caller memory.
+ *   - Code layout: a code of `bits` bits is bits/64 little-endian uint64 words;
+ *     bit j of the code is bit (j % 64) of word (j / 64). Codes are rows of a
+ *     row-major [n][bits/64] array.
+ *   - Graph layout: out_idx [n][K] uint32 and out_dist [n][K] uint16, row i
+ *     holding the K smallest (distance, index) pairs over j != i, ascending in
+ *     distance then index. A row with fewer than K candidates is padded with
+ *     index BDG_NO_IDX and distance BDG_NO_DIST.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     The *_ex / stream-taking calls only enqueue work and return; results are
+ *     ready when the stream reaches that point.
+ *   - Return value: BDG_OK (0) or a negative bdg_status. On an argument error
+ *     (BDG_EINVAL, BDG_EUNSUPPORTED) nothing is enqueued and outputs are
+ *     untouched. On BDG_EDEVICE / BDG_ENOMEM outputs are unspecified;
+ *     bdg_last_error() gives the message (thread-local).
+ *   - Calls on distinct streams may run concurrently from several threads.
+ */
+#ifndef BDG_H_
+#define BDG_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BDG_VERSION 10000 /* 1.0.0 */
+
+#define BDG_NO_IDX 0xFFFFFFFFu
+#define BDG_NO_DIST 0xFFFFu
+#define BDG_MAX_BITS 1024u
+#define BDG_MAX_K 256u
+
+typedef enum bdg_status {
+    BDG_OK = 0,
+    BDG_EINVAL = -1,       /* null pointer, K == 0, bits % 64 != 0, L == 0, ... */
+    BDG_EUNSUPPORTED = -2, /* bits > BDG_MAX_BITS, K > BDG_MAX_K, n == 0xFFFFFFFF */
+    BDG_ENOMEM = -3,       /* workspace allocation failed or workspace too small */
+    BDG_EDEVICE = -4       /* a HIP call failed (message in bdg_last_error) */
+} bdg_status;
+
+/* Which distance tile computes the Hamming distances. Both give identical
+ * graphs: XOR + popcount on the vector ALUs, or an exact +-1 int8 matrix-core
+ * contraction with ham = popcount(q) - <a, 2q - 1>. */
+typedef enum bdg_path {
+    BDG_PATH_AUTO = 0,
+    BDG_PATH_POPC = 1,
+    BDG_PATH_MFMA = 2
+} bdg_path;
+
+/* Options. Zero-initialise and set struct_size = sizeof(bdg_knn_opts); every
+ * zero field takes its default. */
+typedef struct bdg_knn_opts {
+    uint32_t struct_size;
+    int32_t path;            /* bdg_path; default AUTO */
+    uint32_t row_block;      /* rows per row block (default 131072) */
+    uint32_t col_block;      /* columns per column block (default 131072,
+                                at most 2097152) */
+    void *workspace;         /* optional device scratch; if NULL the library
+                                allocates stream-ordered and frees before return */
+    size_t workspace_bytes;  /* size of `workspace` */
+    uint32_t first_rowblock; /* resume: start at this row block (default 0) */
+    uint32_t stop_rowblock;  /* stop before this row block (0 = run to the end) */
+    uint32_t tile_variant;   /* reserved for tile-shape selection; 0 */
+    uint32_t n_tile_events;  /* length of tile_events (0 = no timing) */
+    void **tile_events;      /* optional caller-created hipEvent_t handles: for
+                                the i-th tile launch of the call (one per row
+                                block, in order), events [2i] and [2i + 1] are
+                                recorded on the stream just before and just
+                                after it, while 2i + 1 < n_tile_events */
+    uint32_t reserved[4];
+} bdg_knn_opts;
+
+/* ---------------------------------------------------------------- build --- */
+
+/*
+ * Exact Hamming kNN graph of one partition (Sec. 3.2, first reduce: every
+ * record of the partition is a query against all of its records).
+ *   codes   [n][bits/64] uint64, device
+ *   n       number of codes (0 is a no-op)
+ *   bits    code length, a multiple of 64, at most BDG_MAX_BITS
+ *   K       neighbours per row, 1..BDG_MAX_K
+ *   out_idx [n][K] uint32, out_dist [n][K] uint16, device
+ * Runs on the default stream and returns after completion.
+ */
+int bdg_build_knn(const uint64_t *codes, uint32_t n, uint32_t bits, uint32_t K,
+                  uint32_t *out_idx, uint16_t *out_dist);
+
+/* As bdg_build_knn, enqueued on `stream` with options (opts may be NULL). The
+ * graph is built blockwise: row blocks x column blocks; each column block
+ * yields per-row top-K lists that are merged (as bdg_merge_lists) into the
+ * output. With opts->workspace set, the call allocates nothing. */
+int bdg_build_knn_ex(const uint64_t *codes, uint32_t n, uint32_t bits, uint32_t K,
+                     uint32_t *out_idx, uint16_t *out_dist, const bdg_knn_opts *opts,
+                     void *stream);
+
+/* Workspace bytes bdg_build_knn_ex needs for these arguments (0 if none). */
+int bdg_build_knn_workspace_size(uint32_t n, uint32_t bits, uint32_t K,
+                                 const bdg_knn_opts *opts, size_t *bytes);
+
+/*
+ * Merge neighbour lists (Sec. 3.2 second reduce; Sec. 3.3 merge-sort).
+ *   in_idx/in_dist  [L][n][K_in], each list sorted by (dist, idx) and possibly
+ *                   padded with sentinels (BDG_NO_IDX, BDG_NO_DIST)
+ *   out_idx/out_dist [n][K]
+ * Row r of the output = the K smallest distinct (dist, idx) pairs of the
+ * union of the L lists of row r, ascending, sentinel-padded. An index must
+ * carry the same distance wherever it appears. K_in, K in 1..BDG_MAX_K.
+ */
+int bdg_merge_lists(const uint32_t *in_idx, const uint16_t *in_dist, uint32_t n, uint32_t L,
+                    uint32_t K_in, uint32_t K, uint32_t *out_idx, uint16_t *out_dist,
+                    void *stream);
+
+/* ------------------------------------------------------------ diagnostics --- */
+
+const char *bdg_status_string(int status);
+/* Message of the last failed call on this thread ("" if none). */
+const char *bdg_last_error(void);
+int bdg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BDG_H_ */

@@ -1,0 +1,247 @@
+// Host driver and C ABI of the Hamming kNN-graph builder.
+//
+// Blockwise schedule: rows are cut into row blocks, columns into column
+// blocks. One tile launch per row block computes, for every (row, column
+// block), the exact top-K of that block (the per-partition search of the
+// first reduce, Sec. 3.2). With more than one column block the per-block
+// lists land in a workspace and are merged into the output rows (the second
+// reduce's merge, Sec. 3.2). Row blocks are independent units, so a run can
+// stop after any row block and be resumed from the next one.
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+
+#include "../../include/bdg.h"
+#include "kernels.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int set_error(int status, const char* fmt, ...) {
+  char msg[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(msg, sizeof msg, fmt, ap);
+  va_end(ap);
+  g_last_error = msg;
+  return status;
+}
+
+int device_error(hipError_t e, const char* what) {
+  return set_error(BDG_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr uint32_t kDefaultBlock = 131072;
+constexpr uint32_t kMaxColBlock = 1u << 21;  // column index field of a tile key
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Test hook: BDG_TEST_FAIL_ALLOC=1 makes workspace allocations fail.
+bool forced_alloc_failure() {
+  const char* s = getenv("BDG_TEST_FAIL_ALLOC");
+  return s && s[0] == '1';
+}
+
+struct Plan {
+  uint32_t words, K, n;
+  uint32_t row_block, col_block, nrb, ncb;
+  int path;
+  size_t ws_bytes;  // partial lists of one row block (0 when ncb == 1)
+  size_t ws_idx_off, ws_dist_off;
+};
+
+int path_auto(uint32_t words, uint32_t K) {
+  if (bdg::tile_supported(bdg::kPathMfma, words, K)) return bdg::kPathMfma;
+  return bdg::kPathPopc;
+}
+
+int make_plan(uint32_t n, uint32_t bits, uint32_t K, const bdg_knn_opts* opts, Plan* p) {
+  if (opts && opts->struct_size < offsetof(bdg_knn_opts, workspace))
+    return set_error(BDG_EINVAL, "opts->struct_size too small (%u)", opts->struct_size);
+  if (bits == 0 || bits % 64 != 0)
+    return set_error(BDG_EINVAL, "bits must be a positive multiple of 64 (got %u)", bits);
+  if (bits > BDG_MAX_BITS) return set_error(BDG_EUNSUPPORTED, "bits > %u", BDG_MAX_BITS);
+  if (K == 0) return set_error(BDG_EINVAL, "K must be >= 1");
+  if (K > BDG_MAX_K) return set_error(BDG_EUNSUPPORTED, "K > %u", BDG_MAX_K);
+  if (n == 0xFFFFFFFFu) return set_error(BDG_EUNSUPPORTED, "n must be < 2^32 - 1");
+  p->words = bits / 64;
+  p->K = K;
+  p->n = n;
+  int path = opts ? opts->path : BDG_PATH_AUTO;
+  if (path == BDG_PATH_AUTO) path = path_auto(p->words, K);
+  if (path != BDG_PATH_POPC && path != BDG_PATH_MFMA)
+    return set_error(BDG_EINVAL, "unknown path %d", path);
+  if (!bdg::tile_supported(path, p->words, K))
+    return set_error(BDG_EUNSUPPORTED, "path %d does not support bits=%u K=%u", path, bits, K);
+  p->path = path;
+  uint32_t cb = (opts && opts->col_block) ? opts->col_block : kDefaultBlock;
+  uint32_t rb = (opts && opts->row_block) ? opts->row_block : kDefaultBlock;
+  if (cb > kMaxColBlock)
+    return set_error(BDG_EUNSUPPORTED, "col_block > %u", kMaxColBlock);
+  if (n > 0) {
+    if (cb > n) cb = n;
+    if (rb > n) rb = n;
+  }
+  p->col_block = cb;
+  p->row_block = rb;
+  p->ncb = n ? (n + cb - 1) / cb : 0;
+  p->nrb = n ? (n + rb - 1) / rb : 0;
+  if (p->ncb > 65535)
+    return set_error(BDG_EUNSUPPORTED, "more than 65535 column blocks (col_block %u)", cb);
+  if (p->ncb > 1) {
+    const size_t entries = (size_t)p->ncb * rb * K;
+    p->ws_idx_off = 0;
+    p->ws_dist_off = align256(entries * 4);
+    p->ws_bytes = p->ws_dist_off + align256(entries * 2);
+  } else {
+    p->ws_bytes = p->ws_idx_off = p->ws_dist_off = 0;
+  }
+  return BDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bdg_version(void) { return BDG_VERSION; }
+
+const char* bdg_status_string(int status) {
+  switch (status) {
+    case BDG_OK: return "ok";
+    case BDG_EINVAL: return "invalid argument";
+    case BDG_EUNSUPPORTED: return "unsupported argument";
+    case BDG_ENOMEM: return "out of device memory";
+    case BDG_EDEVICE: return "device error";
+    default: return "unknown status";
+  }
+}
+
+const char* bdg_last_error(void) { return g_last_error.c_str(); }
+
+int bdg_build_knn_workspace_size(uint32_t n, uint32_t bits, uint32_t K, const bdg_knn_opts* opts,
+                                 size_t* bytes) {
+  if (!bytes) return set_error(BDG_EINVAL, "bytes is NULL");
+  Plan p;
+  int st = make_plan(n, bits, K, opts, &p);
+  if (st != BDG_OK) return st;
+  *bytes = p.ws_bytes;
+  return BDG_OK;
+}
+
+int bdg_build_knn_ex(const uint64_t* codes, uint32_t n, uint32_t bits, uint32_t K,
+                     uint32_t* out_idx, uint16_t* out_dist, const bdg_knn_opts* opts,
+                     void* stream_) {
+  g_last_error.clear();
+  Plan p;
+  int st = make_plan(n, bits, K, opts, &p);
+  if (st != BDG_OK) return st;
+  if (n == 0) return BDG_OK;
+  if (!codes || !out_idx || !out_dist) return set_error(BDG_EINVAL, "null device pointer");
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+
+  uint32_t first = opts ? opts->first_rowblock : 0;
+  uint32_t stop = (opts && opts->stop_rowblock) ? opts->stop_rowblock : p.nrb;
+  if (stop > p.nrb) stop = p.nrb;
+  if (first >= stop) return BDG_OK;
+
+  (void)hipGetLastError();  // start from a clean per-thread error state
+  void* ws = nullptr;
+  bool own_ws = false;
+  if (p.ws_bytes) {
+    if (opts && opts->workspace) {
+      if (opts->workspace_bytes < p.ws_bytes)
+        return set_error(BDG_ENOMEM, "workspace too small: %zu < %zu bytes",
+                         opts->workspace_bytes, p.ws_bytes);
+      ws = opts->workspace;
+    } else {
+      if (forced_alloc_failure())
+        return set_error(BDG_ENOMEM, "workspace allocation failed (forced by test hook)");
+      hipError_t e = hipMallocAsync(&ws, p.ws_bytes, stream);
+      if (e != hipSuccess || !ws) {
+        (void)hipGetLastError();
+        return set_error(BDG_ENOMEM, "workspace allocation of %zu bytes failed", p.ws_bytes);
+      }
+      own_ws = true;
+    }
+  }
+
+  int result = BDG_OK;
+  for (uint32_t rb = first; rb < stop; ++rb) {
+    const uint32_t r0 = rb * p.row_block;
+    const uint32_t nr = (n - r0 < p.row_block) ? n - r0 : p.row_block;
+    bdg::TileArgs a;
+    a.codes = codes;
+    a.words = p.words;
+    a.K = K;
+    a.row0 = r0;
+    a.nrows = nr;
+    a.col0 = 0;
+    a.col1 = n;
+    a.col_block = p.col_block;
+    if (p.ncb == 1) {
+      a.out_idx = out_idx + (size_t)r0 * K;
+      a.out_dist = out_dist + (size_t)r0 * K;
+    } else {
+      a.out_idx = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + p.ws_idx_off);
+      a.out_dist = reinterpret_cast<uint16_t*>(static_cast<char*>(ws) + p.ws_dist_off);
+    }
+    const uint32_t ev = 2 * (rb - first);
+    const bool timed = opts && opts->tile_events && ev + 1 < opts->n_tile_events;
+    hipError_t e = hipSuccess;
+    if (timed) e = hipEventRecord(reinterpret_cast<hipEvent_t>(opts->tile_events[ev]), stream);
+    if (e == hipSuccess) e = bdg::launch_tile(p.path, a, stream);
+    if (e == hipSuccess && timed)
+      e = hipEventRecord(reinterpret_cast<hipEvent_t>(opts->tile_events[ev + 1]), stream);
+    if (e != hipSuccess) {
+      result = device_error(e, "tile launch");
+      break;
+    }
+    if (p.ncb > 1) {
+      e = bdg::launch_merge(a.out_idx, a.out_dist, nr, p.ncb, K, K, out_idx + (size_t)r0 * K,
+                            out_dist + (size_t)r0 * K, /*dedup=*/0, stream);
+      if (e != hipSuccess) {
+        result = device_error(e, "merge launch");
+        break;
+      }
+    }
+  }
+  if (own_ws) {
+    hipError_t e = hipFreeAsync(ws, stream);
+    if (e != hipSuccess && result == BDG_OK) result = device_error(e, "workspace free");
+  }
+  return result;
+}
+
+int bdg_build_knn(const uint64_t* codes, uint32_t n, uint32_t bits, uint32_t K, uint32_t* out_idx,
+                  uint16_t* out_dist) {
+  int st = bdg_build_knn_ex(codes, n, bits, K, out_idx, out_dist, nullptr, nullptr);
+  if (st != BDG_OK || n == 0) return st;
+  hipError_t e = hipStreamSynchronize(nullptr);
+  if (e != hipSuccess) return device_error(e, "synchronize");
+  return BDG_OK;
+}
+
+int bdg_merge_lists(const uint32_t* in_idx, const uint16_t* in_dist, uint32_t n, uint32_t L,
+                    uint32_t K_in, uint32_t K, uint32_t* out_idx, uint16_t* out_dist,
+                    void* stream) {
+  g_last_error.clear();
+  if (L == 0) return set_error(BDG_EINVAL, "L must be >= 1");
+  if (K == 0 || K_in == 0) return set_error(BDG_EINVAL, "K and K_in must be >= 1");
+  if (K > BDG_MAX_K || K_in > BDG_MAX_K)
+    return set_error(BDG_EUNSUPPORTED, "K or K_in > %u", BDG_MAX_K);
+  if (n == 0) return BDG_OK;
+  if (!in_idx || !in_dist || !out_idx || !out_dist)
+    return set_error(BDG_EINVAL, "null device pointer");
+  (void)hipGetLastError();
+  hipError_t e = bdg::launch_merge(in_idx, in_dist, n, L, K_in, K, out_idx, out_dist,
+                                   /*dedup=*/1, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_error(e, "merge launch");
+  return BDG_OK;
+}
+
+}  // extern "C"

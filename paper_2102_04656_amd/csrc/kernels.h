@@ -1,0 +1,37 @@
+// Internal interface between the host driver (bdg_api.hip) and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace bdg {
+
+enum TilePath { kPathPopc = 1, kPathMfma = 2 };
+
+// One launch of a distance tile: rows [row0, row0 + nrows) of `codes` are the
+// queries; columns [col0, col1) are split into blocks of `col_block` columns,
+// one grid row per block. Block b writes its per-row top-K lists to
+//   out_idx/out_dist + (b * nrows + r) * K     (r = row - row0)
+// with global column indices.
+struct TileArgs {
+  const uint64_t* codes;
+  uint32_t words;  // bits / 64
+  uint32_t K;
+  uint32_t row0, nrows;
+  uint32_t col0, col1, col_block;
+  uint32_t* out_idx;
+  uint16_t* out_dist;
+};
+
+bool tile_supported(int path, uint32_t words, uint32_t K);
+// Rows of one tile (work-group) for a path.
+uint32_t tile_rows(int path, uint32_t words);
+hipError_t launch_tile(int path, const TileArgs& a, hipStream_t stream);
+
+// Merge of L sorted lists per row; dedup = 0 when lists are known disjoint.
+hipError_t launch_merge(const uint32_t* in_idx, const uint16_t* in_dist, uint32_t n, uint32_t L,
+                        uint32_t K_in, uint32_t K, uint32_t* out_idx, uint16_t* out_dist,
+                        int dedup, hipStream_t stream);
+
+}  // namespace bdg

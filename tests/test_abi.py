@@ -1,0 +1,95 @@
+"""The C ABI: the library loads, exports every entry point ``include/bdg.h``
+declares, and rejects bad arguments with the documented status codes before
+touching the GPU (CPU only: no compute call is made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2102_04656_amd import bdg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "bdg.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bdg_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = bdg.lib()
+    syms = declared_symbols()
+    assert "bdg_build_knn" in syms and "bdg_merge_lists" in syms
+    for name in syms:
+        assert hasattr(L, name), f"{name} declared in bdg.h but not exported"
+
+
+def test_binding_covers_header():
+    assert set(declared_symbols()) <= set(bdg.exported_symbols()) | {"bdg_last_error"}
+
+
+def test_version_and_status_strings():
+    assert bdg.bdg_version() == 10000
+    assert bdg.bdg_status_string(0) == "ok"
+    assert bdg.bdg_status_string(-1) == "invalid argument"
+    assert bdg.bdg_status_string(-4) == "device error"
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation
+
+
+def call_ex(n=10, bits=128, K=4, codes=FAKE, oi=FAKE, od=FAKE, opts=None):
+    L = bdg.lib()
+    op = ctypes.byref(opts) if opts is not None else None
+    return L.bdg_build_knn_ex(codes, n, bits, K, oi, od, op, None)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(bits=0), bdg.BDG_EINVAL),
+    (dict(bits=100), bdg.BDG_EINVAL),
+    (dict(bits=1088), bdg.BDG_EUNSUPPORTED),
+    (dict(K=0), bdg.BDG_EINVAL),
+    (dict(K=257), bdg.BDG_EUNSUPPORTED),
+    (dict(n=0xFFFFFFFF), bdg.BDG_EUNSUPPORTED),
+    (dict(codes=None), bdg.BDG_EINVAL),
+    (dict(oi=None), bdg.BDG_EINVAL),
+    (dict(od=None), bdg.BDG_EINVAL),
+    (dict(opts=bdg.make_opts(path=7)), bdg.BDG_EINVAL),
+    (dict(opts=bdg.make_opts(col_block=(1 << 21) + 1)), bdg.BDG_EUNSUPPORTED),
+])
+def test_build_rejects_bad_arguments(kw, status):
+    assert call_ex(**kw) == status
+    assert bdg.last_error() != ""
+
+
+def test_small_struct_size_rejected():
+    o = bdg.make_opts()
+    o.struct_size = 4
+    assert call_ex(opts=o) == bdg.BDG_EINVAL
+
+
+def test_empty_input_is_a_noop():
+    assert call_ex(n=0, codes=None, oi=None, od=None) == bdg.BDG_OK
+    L = bdg.lib()
+    assert L.bdg_build_knn(None, 0, 256, 8, None, None) == bdg.BDG_OK
+
+
+def test_workspace_size():
+    # one column block: no workspace; several: L * row_block * K * (4 + 2) bytes, aligned
+    assert bdg.bdg_build_knn_workspace_size(1000, 256, 8) == 0
+    o = bdg.make_opts(col_block=250, row_block=300)
+    ws = bdg.bdg_build_knn_workspace_size(1000, 256, 8, o)
+    ent = 4 * 300 * 8
+    assert ws == ((ent * 4 + 255) // 256) * 256 + ((ent * 2 + 255) // 256) * 256
+
+
+def test_merge_rejects_bad_arguments():
+    L = bdg.lib()
+    assert L.bdg_merge_lists(FAKE, FAKE, 10, 0, 4, 4, FAKE, FAKE, None) == bdg.BDG_EINVAL
+    assert L.bdg_merge_lists(FAKE, FAKE, 10, 2, 0, 4, FAKE, FAKE, None) == bdg.BDG_EINVAL
+    assert L.bdg_merge_lists(FAKE, FAKE, 10, 2, 4, 0, FAKE, FAKE, None) == bdg.BDG_EINVAL
+    assert L.bdg_merge_lists(FAKE, FAKE, 10, 2, 4, 300, FAKE, FAKE, None) == bdg.BDG_EUNSUPPORTED
+    assert L.bdg_merge_lists(None, FAKE, 10, 2, 4, 4, FAKE, FAKE, None) == bdg.BDG_EINVAL
+    assert L.bdg_merge_lists(None, None, 0, 2, 4, 4, None, None, None) == bdg.BDG_OK

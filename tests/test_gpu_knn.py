@@ -1,0 +1,239 @@
+"""GPU parity: the HIP graph builder (through the C ABI) against the CPU oracle.
+
+Integer work, so the bar is bit-exact equality of indices and distances. The
+(distance, index) order makes every row unique, ties included.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2102_04656_amd import bdg, datagen
+from tests import golden_io
+
+pytestmark = pytest.mark.gpu
+
+POPC, MFMA = bdg.PATH_POPC, bdg.PATH_MFMA
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    bdg.lib()
+
+
+def dev(codes):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(codes).view(np.int64)).cuda()
+
+
+def gpu_knn(codes, K, path, **kw):
+    import torch
+    idx, dist = bdg.build_knn(dev(codes), K, path=path, **kw)
+    torch.cuda.synchronize()
+    return bdg.to_numpy_graph(idx, dist)
+
+
+def assert_same(got, want, what=""):
+    gi, gd = got
+    wi, wd = want
+    if not (np.array_equal(gi, wi) and np.array_equal(gd, wd)):
+        bad = np.nonzero((gi != wi).any(axis=1) | (gd != wd).any(axis=1))[0]
+        r = int(bad[0])
+        raise AssertionError(f"{what}: {bad.size} rows differ; first row {r}:\n"
+                             f" got  {list(zip(gd[r][:12], gi[r][:12]))}\n"
+                             f" want {list(zip(wd[r][:12], wi[r][:12]))}")
+
+
+# ------------------------------------------------------------ small grid
+
+GRID = [
+    # n, bits, K, n_centres, p
+    (1, 128, 4, 1, 0.1),
+    (2, 64, 1, 1, 0.1),
+    (17, 64, 16, 2, 0.1),
+    (64, 128, 63, 3, 0.1),
+    (65, 192, 64, 3, 0.15),
+    (130, 256, 129, 4, 0.2),
+    (1000, 64, 32, 20, 0.05),
+    (1000, 128, 1, 20, 0.15),
+    (1000, 256, 64, 20, 0.2),
+    (1000, 320, 65, 20, 0.2),
+    (1000, 512, 100, 20, 0.25),
+    (1000, 1024, 33, 10, 0.25),
+    (777, 448, 128, 7, 0.2),
+    (600, 576, 256, 6, 0.2),
+    (3001, 256, 7, 40, 0.2),
+]
+
+
+@pytest.mark.parametrize("path", [POPC, MFMA], ids=["popc", "mfma"])
+@pytest.mark.parametrize("n,bits,K,nc,p", GRID)
+def test_small_grid(path, n, bits, K, nc, p):
+    codes = datagen.clustered_codes(n, bits, nc, p, seed=n * 7 + bits + K)
+    want = oracle.knn_rows(codes, K)
+    assert_same(gpu_knn(codes, K, path), want, f"n={n} bits={bits} K={K}")
+
+
+@pytest.mark.parametrize("path", [POPC, MFMA], ids=["popc", "mfma"])
+@pytest.mark.parametrize("col_block,row_block", [(37, 0), (100, 333), (999, 64), (1, 2000)])
+def test_blocking_does_not_change_the_graph(path, col_block, row_block):
+    codes = datagen.clustered_codes(1500 if col_block > 1 else 200, 256, 15, 0.2, seed=21)
+    want = oracle.knn_rows(codes, 24)
+    got = gpu_knn(codes, 24, path, col_block=col_block, row_block=row_block)
+    assert_same(got, want, f"col_block={col_block} row_block={row_block}")
+
+
+@pytest.mark.parametrize("path", [POPC, MFMA], ids=["popc", "mfma"])
+def test_golden_cube3(path):
+    layouts, exp_idx, exp_dist = golden_io.cube3()
+    for bits, positions, background in layouts:
+        codes = golden_io.cube3_codes(bits, positions, background)
+        got = gpu_knn(codes, 7, path)
+        assert_same(got, (exp_idx, exp_dist), f"cube3 bits={bits}")
+
+
+@pytest.mark.parametrize("path", [POPC, MFMA], ids=["popc", "mfma"])
+def test_tie_heavy_inputs(path):
+    # all codes identical: every distance 0, neighbours are the smallest indices
+    codes = np.tile(datagen.uniform_codes(1, 256, seed=5), (300, 1))
+    assert_same(gpu_knn(codes, 50, path), oracle.knn_rows(codes, 50), "identical")
+    # 10-cube: 1024 codes, distances 1..10 with binomial multiplicities
+    rows = np.array([[(v >> t) & 1 for t in range(10)] + [0] * 118 for v in range(1024)],
+                    dtype=np.uint8)
+    codes = datagen.pack_bits(rows)
+    for K in (10, 256):
+        assert_same(gpu_knn(codes, K, path), oracle.knn_rows(codes, K), f"cube10 K={K}")
+
+
+def test_paths_agree_and_are_deterministic():
+    codes = datagen.clustered_codes(5000, 256, 50, 0.2, seed=31)
+    a = gpu_knn(codes, 64, POPC)
+    b = gpu_knn(codes, 64, MFMA)
+    assert_same(a, b, "popc vs mfma")
+    for cb in (5000, 1024, 333):
+        assert_same(gpu_knn(codes, 64, MFMA, col_block=cb), a, f"mfma col_block={cb}")
+        assert_same(gpu_knn(codes, 64, POPC, col_block=cb), a, f"popc col_block={cb}")
+
+
+# ------------------------------------------------------ named workloads
+
+def test_clustered_20k_128b_k32_full():
+    """20,000 codes of 128 bits from 100 centres (flip 0.15), K = 32: every row."""
+    w = datagen.WORKLOADS["clustered-20k-128b-k32"]
+    codes = datagen.clustered_codes(w["n"], w["bits"], w["n_centres"], w["p"], w["seed"])
+    want = oracle.knn_rows(codes, w["K"])
+    for path in (POPC, MFMA):
+        assert_same(gpu_knn(codes, w["K"], path), want, f"path={path}")
+
+
+def test_clustered_1m_256b_k64_sampled():
+    """1,000,000 codes of 256 bits from 1,000 centres (flip 0.2), K = 64, built in
+    131072 x 131072 blocks with merged per-block lists, as timed by the
+    benchmark. Both paths agree on every row; the oracle checks sampled rows
+    (block edges, ends, and random rows)."""
+    w = datagen.WORKLOADS["clustered-1m-256b-k64"]
+    codes = datagen.clustered_codes(w["n"], w["bits"], w["n_centres"], w["p"], w["seed"])
+    K, n = w["K"], w["n"]
+    kw = dict(row_block=w["row_block"], col_block=w["col_block"])
+    a = gpu_knn(codes, K, MFMA, **kw)
+    b = gpu_knn(codes, K, POPC, **kw)
+    assert_same(a, b, "mfma vs popc")
+    g = np.random.default_rng(99)
+    edges = [0, 1, 131071, 131072, 131073, 2 * 131072 - 1, n - 131072, n - 2, n - 1]
+    rows = np.unique(np.concatenate([edges, g.choice(n, 300, replace=False)])).astype(np.uint32)
+    want = oracle.knn_rows(codes, K, rows=rows)
+    assert_same((a[0][rows], a[1][rows]), want, "oracle rows")
+
+
+# ----------------------------------------------------------------- merge
+
+def test_merge_golden():
+    import torch
+    K, in_idx, in_dist, out_idx, out_dist = golden_io.merge_small()
+    ti = torch.from_numpy(in_idx.view(np.int32)).cuda()
+    td = torch.from_numpy(in_dist.view(np.int16)).cuda()
+    got = bdg.to_numpy_graph(*bdg.merge_lists(ti, td, K))
+    assert_same(got, (out_idx, out_dist), "merge golden")
+
+
+@pytest.mark.parametrize("K_in,K", [(16, 16), (64, 32), (100, 100), (40, 128), (256, 256)])
+def test_merge_api_with_duplicates(K_in, K):
+    import torch
+    codes = datagen.clustered_codes(2000, 128, 25, 0.15, seed=K_in + K)
+    bi, bd = oracle.knn_blocks(codes, K_in, col_block=450)
+    # add repeated lists (a copy and a shifted copy of the same blocks)
+    bi = np.concatenate([bi, bi[:2], bi[1:3]])
+    bd = np.concatenate([bd, bd[:2], bd[1:3]])
+    rows = np.arange(0, 2000, 13)
+    want = oracle.merge_lists(bi[:, rows], bd[:, rows], K)
+    ti = torch.from_numpy(np.ascontiguousarray(bi).view(np.int32)).cuda()
+    td = torch.from_numpy(np.ascontiguousarray(bd).view(np.int16)).cuda()
+    gi, gd = bdg.to_numpy_graph(*bdg.merge_lists(ti, td, K))
+    assert_same((gi[rows], gd[rows]), want, "merge")
+
+
+# ------------------------------------------------- driver: resume, workspace
+
+def test_resume_by_row_blocks():
+    import torch
+    codes = datagen.clustered_codes(3000, 256, 30, 0.2, seed=41)
+    K = 16
+    want = gpu_knn(codes, K, MFMA, row_block=700, col_block=1000)
+    d = dev(codes)
+    idx = torch.full((3000, K), -7, dtype=torch.int32, device="cuda")
+    dist = torch.full((3000, K), -7, dtype=torch.int16, device="cuda")
+    for first, stop in ((0, 2), (2, 3), (3, 0)):
+        o = bdg.make_opts(path=MFMA, row_block=700, col_block=1000, first_rowblock=first,
+                          stop_rowblock=stop)
+        assert bdg.bdg_build_knn_ex(d, 3000, 256, K, idx, dist, o, None) == 0
+        if first == 0:
+            torch.cuda.synchronize()
+            part = bdg.to_numpy_graph(idx, dist)
+            assert (part[0][1400:] == np.uint32(0xFFFFFFF9)).all()  # untouched beyond block 2
+    torch.cuda.synchronize()
+    assert_same(bdg.to_numpy_graph(idx, dist), want, "resumed")
+
+
+def test_caller_workspace_and_alloc_failure():
+    import torch
+    codes = datagen.clustered_codes(2500, 128, 25, 0.15, seed=43)
+    K = 20
+    want = oracle.knn_rows(codes, K)
+    d = dev(codes)
+    o = bdg.make_opts(col_block=600)
+    need = bdg.bdg_build_knn_workspace_size(2500, 128, K, o)
+    assert need > 0
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    o.workspace, o.workspace_bytes = ws.data_ptr(), need
+    idx = torch.empty((2500, K), dtype=torch.int32, device="cuda")
+    dist = torch.empty((2500, K), dtype=torch.int16, device="cuda")
+    assert bdg.bdg_build_knn_ex(d, 2500, 128, K, idx, dist, o, None) == 0
+    torch.cuda.synchronize()
+    assert_same(bdg.to_numpy_graph(idx, dist), want, "caller workspace")
+    # too small a workspace -> ENOMEM, outputs untouched
+    o.workspace_bytes = need - 1
+    idx.fill_(5)
+    assert bdg.bdg_build_knn_ex(d, 2500, 128, K, idx, dist, o, None) == bdg.BDG_ENOMEM
+    # forced allocation failure -> ENOMEM, outputs untouched
+    os.environ["BDG_TEST_FAIL_ALLOC"] = "1"
+    try:
+        o2 = bdg.make_opts(col_block=600)
+        assert bdg.bdg_build_knn_ex(d, 2500, 128, K, idx, dist, o2, None) == bdg.BDG_ENOMEM
+    finally:
+        del os.environ["BDG_TEST_FAIL_ALLOC"]
+    torch.cuda.synchronize()
+    assert (idx.cpu().numpy() == 5).all()
+
+
+def test_sync_entry_point():
+    import torch
+    codes = datagen.clustered_codes(900, 192, 9, 0.2, seed=47)
+    d = dev(codes)
+    idx = torch.empty((900, 12), dtype=torch.int32, device="cuda")
+    dist = torch.empty((900, 12), dtype=torch.int16, device="cuda")
+    assert bdg.bdg_build_knn(d, 900, 192, 12, idx, dist) == 0
+    assert_same(bdg.to_numpy_graph(idx, dist), oracle.knn_rows(codes, 12), "sync")
