@@ -29,6 +29,8 @@ CXXFLAGS = [
     "-Wno-unused-result",
     # packed FP32 instructions are kept out of every device code object
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core accumulators in VGPRs: results feed VALU compares directly
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 
