@@ -74,15 +74,26 @@ class HipEvents:
 
 
 def run_path(codes_dev, n, bits, K, path, row_block, col_block, steps, warmup):
-    """Time `steps` full builds; returns (ms/step, tile kernel stats, outputs)."""
+    """Time `steps` full builds; returns (ms/step, tile kernel stats, outputs).
+
+    The distance-tile launches of one build are, in order: one per row block
+    (popc: all columns, per-block lists merged afterwards) or one per (row
+    block, column block) pair (mfma: lists carried across column blocks)."""
     import torch
     from paper_2102_04656_amd import bdg
 
     nrb = (n + row_block - 1) // row_block
+    ncb = (n + col_block - 1) // col_block
+    if path == bdg.PATH_MFMA:
+        shapes = [(min(row_block, n - r * row_block), min(col_block, n - c * col_block))
+                  for r in range(nrb) for c in range(ncb)]
+    else:
+        shapes = [(min(row_block, n - r * row_block), n) for r in range(nrb)]
+    nl = len(shapes)
     idx = torch.empty((n, K), dtype=torch.int32, device="cuda")
     dist = torch.empty((n, K), dtype=torch.int16, device="cuda")
     stream = torch.cuda.current_stream()
-    ev = HipEvents(2 * nrb * steps)
+    ev = HipEvents(2 * nl * steps)
     # workspace allocated once, outside the timed region
     o = bdg.make_opts(path=path, row_block=row_block, col_block=col_block)
     ws_bytes = bdg.bdg_build_knn_workspace_size(n, bits, K, o)
@@ -92,8 +103,8 @@ def run_path(codes_dev, n, bits, K, path, row_block, col_block, steps, warmup):
         op = bdg.make_opts(path=path, row_block=row_block, col_block=col_block,
                            workspace=ws.data_ptr(), workspace_bytes=ws_bytes)
         if s is not None:
-            op.n_tile_events = 2 * nrb
-            op.tile_events = ev.slice_ptr(2 * nrb * s)
+            op.n_tile_events = 2 * nl
+            op.tile_events = ev.slice_ptr(2 * nl * s)
         st = bdg.bdg_build_knn_ex(codes_dev, n, bits, K, idx, dist, op, stream)
         if st != 0:
             raise RuntimeError(f"bdg_build_knn_ex failed: {st} {bdg.last_error()}")
@@ -109,12 +120,12 @@ def run_path(codes_dev, n, bits, K, path, row_block, col_block, steps, warmup):
     ms_step = (t1 - t0) * 1e3 / steps
     durs, pairs = [], []
     for s in range(steps):
-        for rb in range(nrb):
-            e = 2 * nrb * s + 2 * rb
+        for i, (rows, cols) in enumerate(shapes):
+            e = 2 * nl * s + 2 * i
             durs.append(ev.elapsed_ms(e, e + 1))
-            rows = min(row_block, n - rb * row_block)
-            pairs.append(rows * (n - 1))
+            pairs.append(rows * cols)
     ev.close()
+    # pairs per launch x launches / total kernel time = pairs / (average duration)
     return ms_step, dict(launches=len(durs), avg_ms=float(np.mean(durs)),
                          pairs_per_launch=float(np.mean(pairs)),
                          total_ms=float(np.sum(durs))), (idx, dist)

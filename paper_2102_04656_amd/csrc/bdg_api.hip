@@ -15,7 +15,7 @@
 
 #include <string>
 
-#include "../../include/bdg.h"
+#include "bdg.h"
 #include "kernels.h"
 
 namespace {
@@ -51,12 +51,13 @@ struct Plan {
   uint32_t words, K, n;
   uint32_t row_block, col_block, nrb, ncb;
   int path;
-  size_t ws_bytes;  // partial lists of one row block (0 when ncb == 1)
+  bool running;     // lists carried across column blocks in the output rows
+  size_t ws_bytes;  // operand fragments (running) or partial lists of one row block
   size_t ws_idx_off, ws_dist_off;
 };
 
-int path_auto(uint32_t words, uint32_t K) {
-  if (bdg::tile_supported(bdg::kPathMfma, words, K)) return bdg::kPathMfma;
+int path_auto(uint32_t n, uint32_t words, uint32_t K) {
+  if (bdg::run_supported(n, words, K)) return bdg::kPathMfma;
   return bdg::kPathPopc;
 }
 
@@ -73,11 +74,14 @@ int make_plan(uint32_t n, uint32_t bits, uint32_t K, const bdg_knn_opts* opts, P
   p->K = K;
   p->n = n;
   int path = opts ? opts->path : BDG_PATH_AUTO;
-  if (path == BDG_PATH_AUTO) path = path_auto(p->words, K);
+  if (path == BDG_PATH_AUTO) path = path_auto(n, p->words, K);
   if (path != BDG_PATH_POPC && path != BDG_PATH_MFMA)
     return set_error(BDG_EINVAL, "unknown path %d", path);
-  if (!bdg::tile_supported(path, p->words, K))
-    return set_error(BDG_EUNSUPPORTED, "path %d does not support bits=%u K=%u", path, bits, K);
+  const bool ok = path == BDG_PATH_MFMA ? bdg::run_supported(n, p->words, K)
+                                        : bdg::tile_supported(path, p->words, K);
+  if (!ok)
+    return set_error(BDG_EUNSUPPORTED, "path %d does not support n=%u bits=%u K=%u", path, n,
+                     bits, K);
   p->path = path;
   uint32_t cb = (opts && opts->col_block) ? opts->col_block : kDefaultBlock;
   uint32_t rb = (opts && opts->row_block) ? opts->row_block : kDefaultBlock;
@@ -93,7 +97,11 @@ int make_plan(uint32_t n, uint32_t bits, uint32_t K, const bdg_knn_opts* opts, P
   p->nrb = n ? (n + rb - 1) / rb : 0;
   if (p->ncb > 65535)
     return set_error(BDG_EUNSUPPORTED, "more than 65535 column blocks (col_block %u)", cb);
-  if (p->ncb > 1) {
+  p->running = path == BDG_PATH_MFMA;
+  if (p->running) {
+    p->ws_bytes = n ? align256(bdg::prep_bytes(n, p->words)) : 0;
+    p->ws_idx_off = p->ws_dist_off = 0;
+  } else if (p->ncb > 1) {
     const size_t entries = (size_t)p->ncb * rb * K;
     p->ws_idx_off = 0;
     p->ws_dist_off = align256(entries * 4);
@@ -171,7 +179,41 @@ int bdg_build_knn_ex(const uint64_t* codes, uint32_t n, uint32_t bits, uint32_t 
   }
 
   int result = BDG_OK;
-  for (uint32_t rb = first; rb < stop; ++rb) {
+  if (p.running) {
+    // Operand fragments of all codes, then row block x column block tiles,
+    // each merging its columns into the rows' running lists.
+    hipError_t e = bdg::launch_prep(codes, n, p.words, ws, stream);
+    uint32_t launch = 0;
+    for (uint32_t rb = first; rb < stop && e == hipSuccess; ++rb) {
+      const uint32_t r0 = rb * p.row_block;
+      const uint32_t nr = (n - r0 < p.row_block) ? n - r0 : p.row_block;
+      for (uint32_t c = 0; c < p.ncb && e == hipSuccess; ++c, ++launch) {
+        bdg::RunArgs a;
+        a.codes = codes;
+        a.frags = ws;
+        a.words = p.words;
+        a.bits = bits;
+        a.K = K;
+        a.idx_bits = bdg::run_idx_bits(bits);
+        a.row0 = r0;
+        a.nrows = nr;
+        a.cb = c * p.col_block;
+        a.ce = (n - a.cb < p.col_block) ? n : a.cb + p.col_block;
+        a.fresh = c == 0;
+        a.out_idx = out_idx + (size_t)r0 * K;
+        a.out_dist = out_dist + (size_t)r0 * K;
+        const bool timed = opts && opts->tile_events && 2 * launch + 1 < opts->n_tile_events;
+        if (timed)
+          e = hipEventRecord(reinterpret_cast<hipEvent_t>(opts->tile_events[2 * launch]), stream);
+        if (e == hipSuccess) e = bdg::launch_mfma_run(a, stream);
+        if (e == hipSuccess && timed)
+          e = hipEventRecord(reinterpret_cast<hipEvent_t>(opts->tile_events[2 * launch + 1]),
+                             stream);
+      }
+    }
+    if (e != hipSuccess) result = device_error(e, "tile launch");
+  }
+  for (uint32_t rb = first; rb < stop && !p.running; ++rb) {
     const uint32_t r0 = rb * p.row_block;
     const uint32_t nr = (n - r0 < p.row_block) ? n - r0 : p.row_block;
     bdg::TileArgs a;

@@ -34,4 +34,28 @@ hipError_t launch_merge(const uint32_t* in_idx, const uint16_t* in_dist, uint32_
                         uint32_t K_in, uint32_t K, uint32_t* out_idx, uint16_t* out_dist,
                         int dedup, hipStream_t stream);
 
+// Running-merge tile on the int8 matrix cores (tile_mfma.hip). One launch
+// merges columns [cb, ce) into the lists of rows [row0, row0 + nrows); the
+// lists live in out_idx/out_dist (row r at (r - row0) * K), which hold the
+// result of the earlier column blocks unless `fresh`. Keys carry the global
+// column index in idx_bits = run_idx_bits(bits) bits, so n must fit.
+struct RunArgs {
+  const uint64_t* codes;  // packed codes (queries are expanded from these)
+  const void* frags;      // prep output for the same codes
+  uint32_t words, bits, K, idx_bits;
+  uint32_t row0, nrows, cb, ce;
+  int fresh;
+  uint32_t* out_idx;
+  uint16_t* out_dist;
+};
+
+uint32_t run_idx_bits(uint32_t bits);
+bool run_supported(uint32_t n, uint32_t words, uint32_t K);
+uint32_t run_rows_per_wg(uint32_t K);
+// Operand prep: +-1 int8 fragments of every code, prep_bytes(n, words) bytes.
+size_t prep_bytes(uint32_t n, uint32_t words);
+hipError_t launch_prep(const uint64_t* codes, uint32_t n, uint32_t words, void* frags,
+                       hipStream_t stream);
+hipError_t launch_mfma_run(const RunArgs& a, hipStream_t stream);
+
 }  // namespace bdg

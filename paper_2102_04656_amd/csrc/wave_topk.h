@@ -29,29 +29,68 @@ constexpr uint32_t kDistNone = 0x7FFFu;  // threshold while a list is not full
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
+__device__ __forceinline__ uint32_t umin32(uint32_t a, uint32_t b) { return a < b ? a : b; }
+__device__ __forceinline__ uint32_t umax32(uint32_t a, uint32_t b) { return a < b ? b : a; }
+
+// x of lane (lane ^ M), M a power of two below 64. Masks inside a row of 16
+// lanes use DPP moves (quad permutes for 1 and 2; a row shift each way and a
+// select for 4 and 8), 16 a swizzle inside 32 lanes, 32 a permute.
+template <int M>
+__device__ __forceinline__ uint32_t xshfl(uint32_t x, uint32_t lane) {
+  if constexpr (M == 1) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);
+  } else if constexpr (M == 2) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false);
+  } else if constexpr (M == 4 || M == 8) {
+    const uint32_t up = (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x100 + M, 0xF, 0xF,
+                                                              false);  // lane i <- i + M
+    const uint32_t dn = (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x110 + M, 0xF, 0xF,
+                                                              false);  // lane i <- i - M
+    return (lane & M) ? dn : up;
+  } else if constexpr (M == 16) {
+    return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x401F);
+  } else {
+    static_assert(M == 32, "xor mask");
+    return (uint32_t)__shfl_xor((int)x, 32, kWave);
+  }
+}
+
 __device__ __forceinline__ uint32_t shfl_xor_u32(uint32_t x, int m) {
   return (uint32_t)__shfl_xor((int)x, m, kWave);
+}
+
+// One compare-exchange stage of a bitonic network over one key per lane:
+// keep the min if `take_min`, else the max, of x and the key of lane ^ J.
+template <int J>
+__device__ __forceinline__ uint32_t cx_stage(uint32_t x, uint32_t lane, bool take_min) {
+  const uint32_t y = xshfl<J>(x, lane);
+  return take_min ? umin32(x, y) : umax32(x, y);
 }
 
 __device__ __forceinline__ uint32_t shfl_u32(uint32_t x, int src) {
   return (uint32_t)__shfl((int)x, src, kWave);
 }
 
-__device__ __forceinline__ uint32_t umin32(uint32_t a, uint32_t b) { return a < b ? a : b; }
-__device__ __forceinline__ uint32_t umax32(uint32_t a, uint32_t b) { return a < b ? b : a; }
 
-// Ascending bitonic sort of one key per lane across the wave.
+// Bitonic sort of one key per lane across the wave (ascending, or descending
+// with DESC: every comparison direction flipped).
+template <int K2, int J, bool DESC>
+__device__ __forceinline__ uint32_t sort_steps(uint32_t x, uint32_t lane) {
+  const bool up = ((lane & K2) == 0) != DESC;
+  const bool lower = (lane & J) == 0;
+  x = cx_stage<J>(x, lane, lower == up);
+  if constexpr (J > 1) return sort_steps<K2, J / 2, DESC>(x, lane);
+  return x;
+}
+
+template <bool DESC = false>
 __device__ __forceinline__ uint32_t wave_sort64(uint32_t x, uint32_t lane) {
-#pragma unroll
-  for (int k = 2; k <= kWave; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      uint32_t y = shfl_xor_u32(x, j);
-      bool up = (lane & k) == 0;
-      bool lower = (lane & j) == 0;
-      x = (lower == up) ? umin32(x, y) : umax32(x, y);
-    }
-  }
+  x = sort_steps<2, 1, DESC>(x, lane);
+  x = sort_steps<4, 2, DESC>(x, lane);
+  x = sort_steps<8, 4, DESC>(x, lane);
+  x = sort_steps<16, 8, DESC>(x, lane);
+  x = sort_steps<32, 16, DESC>(x, lane);
+  x = sort_steps<64, 32, DESC>(x, lane);
   return x;
 }
 
@@ -71,32 +110,31 @@ __device__ __forceinline__ void wave_bitonic_merge(uint32_t (&R)[NR], uint32_t l
     }
   }
 #pragma unroll
-  for (int j = kWave / 2; j >= 1; j >>= 1) {
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      uint32_t y = shfl_xor_u32(R[r], j);
-      R[r] = (lane & j) ? umax32(R[r], y) : umin32(R[r], y);
-    }
+  for (int r = 0; r < NR; ++r) {
+    R[r] = cx_stage<32>(R[r], lane, (lane & 32) == 0);
+    R[r] = cx_stage<16>(R[r], lane, (lane & 16) == 0);
+    R[r] = cx_stage<8>(R[r], lane, (lane & 8) == 0);
+    R[r] = cx_stage<4>(R[r], lane, (lane & 4) == 0);
+    R[r] = cx_stage<2>(R[r], lane, (lane & 2) == 0);
+    R[r] = cx_stage<1>(R[r], lane, (lane & 1) == 0);
   }
 }
 
-// Merge the c pending keys of one query into its sorted list (wave-wide; every
-// lane must call it with the same arguments). Returns the new K-th key.
-template <int NR, int B>
-__device__ __forceinline__ uint32_t flush_query(uint32_t* list_q, const uint32_t* buf_q,
-                                                uint32_t c, uint32_t K, uint32_t lane) {
-  static_assert(B <= kWave, "buffer holds at most one key per lane");
-  uint32_t x = (lane < c) ? buf_q[lane] : kKeyNone;
-  x = wave_sort64(x, lane);
-  uint32_t xr = shfl_u32(x, kWave - 1 - lane);  // buffer descending
+// Merge up to 64 new keys (one per lane, any order, kKeyNone for none) into
+// the sorted list of one query (wave-wide; every lane must call it with the
+// same list). Returns the new K-th key (kKeyNone while the list is not full).
+template <int NR>
+__device__ __forceinline__ uint32_t merge_into_list(uint32_t* list_q, uint32_t x, uint32_t K,
+                                                    uint32_t lane) {
+  const uint32_t xr = wave_sort64<true>(x, lane);  // new keys, descending
   uint32_t R[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     uint32_t p = r * kWave + lane;
     R[r] = (p < K) ? list_q[p] : kKeyNone;
   }
-  // min(list[i], buf_padded[N-1-i]) keeps the N smallest of the union as a
-  // bitonic sequence; only the last 64 positions meet real buffer keys.
+  // min(list[i], new_padded[N-1-i]) keeps the N smallest of the union as a
+  // bitonic sequence; only the last 64 positions meet real new keys.
   R[NR - 1] = umin32(R[NR - 1], xr);
   wave_bitonic_merge<NR>(R, lane);
 #pragma unroll
@@ -110,6 +148,15 @@ __device__ __forceinline__ uint32_t flush_query(uint32_t* list_q, const uint32_t
   for (int r = 0; r < NR; ++r)
     if ((last >> 6) == (uint32_t)r) kth = __builtin_amdgcn_readlane(R[r], last & 63);
   return kth;
+}
+
+// Merge the c pending keys buf_q[0..c) of one query into its list.
+template <int NR, int B>
+__device__ __forceinline__ uint32_t flush_query(uint32_t* list_q, const uint32_t* buf_q,
+                                                uint32_t c, uint32_t K, uint32_t lane) {
+  static_assert(B <= kWave, "buffer holds at most one key per lane");
+  const uint32_t x = (lane < c) ? buf_q[lane] : kKeyNone;
+  return merge_into_list<NR>(list_q, x, K, lane);
 }
 
 __device__ __forceinline__ uint32_t key_dist(uint32_t key) {
