@@ -232,7 +232,7 @@ def main():
                    "centres": w["n_centres"], "flip_p": w["p"], "seed": w["seed"]},
         "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TOP/s",
                      "frac": achieved / peak, "traffic": None,
-                     "kernel": f"knn_{main_path}_kernel",
+                     "kernel": "knn_mfma_run_kernel" if main_path == "mfma" else "knn_popc_kernel",
                      "kernel_avg_ms": kern["avg_ms"],
                      "ops_per_pair": ops_pair,
                      "pairs_per_launch": kern["pairs_per_launch"]},
