@@ -76,7 +76,7 @@ typedef struct bdg_knn_opts {
     size_t workspace_bytes;  /* size of `workspace` */
     uint32_t first_rowblock; /* resume: start at this row block (default 0) */
     uint32_t stop_rowblock;  /* stop before this row block (0 = run to the end) */
-    uint32_t tile_variant;   /* reserved for tile-shape selection; 0 */
+    uint32_t tile_variant;   /* batched plans: work order (BDG_ORDER_*); else 0 */
     uint32_t n_tile_events;  /* length of tile_events (0 = no timing) */
     void **tile_events;      /* optional caller-created hipEvent_t handles: for
                                 the i-th tile launch of the call (one per row
@@ -125,6 +125,92 @@ int bdg_build_knn_workspace_size(uint32_t n, uint32_t bits, uint32_t K,
 int bdg_merge_lists(const uint32_t *in_idx, const uint16_t *in_dist, uint32_t n, uint32_t L,
                     uint32_t K_in, uint32_t K, uint32_t *out_idx, uint16_t *out_dist,
                     void *stream);
+
+/* ---------------------------------------------------- many partitions --- */
+
+/*
+ * Many independent partitions in one persistent launch. The single-pass
+ * divide-and-conquer (Sec. 3.2) yields partitions of very uneven size, which
+ * the paper balances over its reduce nodes (Sec. 3.6 (1)); here every
+ * partition (shard) is an exact kNN problem of its own:
+ *   shard s = rows [offsets[s], offsets[s + 1]) of `codes`, searched against
+ *   the same rows only; output row r (global) holds shard-local neighbour
+ *   indices (column - offsets[s]), in the graph layout above.
+ * Rows outside every shard are not written. Work items of up to 256 rows of
+ * one shard are taken from a shared counter by one work-group per CU, longest
+ * first (or in shard order), so one launch balances the uneven shards.
+ *
+ * A plan holds the work list, a counter and the operand workspace (device
+ * memory it allocates once, about bits bytes per row). Launching a plan
+ * allocates nothing, so it can be captured in a HIP graph.
+ */
+typedef struct bdg_batch_plan bdg_batch_plan;
+
+#define BDG_ORDER_LONGEST_FIRST 0 /* work items by decreasing rows x columns */
+#define BDG_ORDER_SHARD 1         /* work items in shard order */
+
+typedef struct bdg_batch_info {
+    uint32_t shards, rows, work_items, workgroups;
+    int32_t order;         /* BDG_ORDER_* */
+    uint64_t pairs;        /* sum over shards of n_s (n_s - 1) */
+    size_t device_bytes;   /* device memory held by the plan */
+} bdg_batch_info;
+
+/*
+ * Build a plan. offsets: HOST array of S + 1 non-decreasing row offsets
+ * (offsets[S] = rows of `codes` used). bits, K as for bdg_build_knn; every
+ * shard must fit the matrix-core path (at most 2^(32 - bits needed for a
+ * distance) - 1 rows). opts may be NULL; opts->tile_variant = BDG_ORDER_SHARD
+ * selects shard order. Allocates device memory (synchronously).
+ */
+int bdg_batch_plan_create(const uint64_t *offsets, uint32_t S, uint32_t bits, uint32_t K,
+                          const bdg_knn_opts *opts, bdg_batch_plan **plan);
+void bdg_batch_plan_destroy(bdg_batch_plan *plan);
+int bdg_batch_plan_info(const bdg_batch_plan *plan, bdg_batch_info *info);
+/* Change the work order (re-uploads the work list; drops a captured graph). */
+int bdg_batch_plan_set_order(bdg_batch_plan *plan, int order);
+
+/* Enqueue the build of every shard on `stream` (operand prep, counter reset,
+ * persistent kernel). Allocates nothing. codes: device [offsets[S]][bits/64];
+ * out_idx/out_dist: device [offsets[S]][K]. */
+int bdg_build_knn_batched_plan(const bdg_batch_plan *plan, const uint64_t *codes,
+                               uint32_t *out_idx, uint16_t *out_dist, void *stream);
+
+/* As bdg_build_knn_batched_plan, through a HIP graph: the first call (or a
+ * call with other pointers) captures the launch sequence on `stream` (which
+ * must not be the default stream) and instantiates it; every call launches
+ * the graph. */
+int bdg_build_knn_batched_graph(bdg_batch_plan *plan, const uint64_t *codes, uint32_t *out_idx,
+                                uint16_t *out_dist, void *stream);
+
+/* One-shot: plan, enqueue on `stream`, wait for completion, free the plan. */
+int bdg_build_knn_batched_ex(const uint64_t *codes, const uint64_t *offsets, uint32_t S,
+                             uint32_t bits, uint32_t K, uint32_t *out_idx, uint16_t *out_dist,
+                             const bdg_knn_opts *opts, void *stream);
+
+/* ------------------------------------------------------------- autotune --- */
+
+/*
+ * Schedule autotuning. Candidates compute the same graph; they are timed with
+ * HIP events on `stream` (one warm-up, then averaged runs) and the fastest is
+ * kept. `report` (may be NULL) receives a JSON object describing the choice
+ * and every candidate's time. With BDG_AUTOTUNE_CACHE set, each choice is
+ * appended to that file as one JSON line (read back by later processes).
+ *
+ * bdg_autotune_build: candidates = matrix-core tile with column blocks of
+ *   65536 / 131072 / 262144 columns, and the vector-ALU tile; writes the
+ *   winner into opts->path and opts->col_block (opts->row_block is used as
+ *   given) and remembers it for (bits, K, floor(log2 n)), so later calls with
+ *   path AUTO and col_block 0 take it. Runs the build several times into
+ *   out_idx/out_dist (device, [n][K]); allocates a workspace for the duration.
+ * bdg_autotune_batched: candidates = the two work orders; keeps the faster in
+ *   the plan.
+ */
+int bdg_autotune_build(const uint64_t *codes, uint32_t n, uint32_t bits, uint32_t K,
+                       uint32_t *out_idx, uint16_t *out_dist, bdg_knn_opts *opts, void *stream,
+                       char *report, size_t report_len);
+int bdg_autotune_batched(bdg_batch_plan *plan, const uint64_t *codes, uint32_t *out_idx,
+                         uint16_t *out_dist, void *stream, char *report, size_t report_len);
 
 /* ------------------------------------------------------------ diagnostics --- */
 

@@ -54,6 +54,21 @@ class KnnOpts(ctypes.Structure):
     ]
 
 
+class BatchInfo(ctypes.Structure):
+    _fields_ = [
+        ("shards", ctypes.c_uint32),
+        ("rows", ctypes.c_uint32),
+        ("work_items", ctypes.c_uint32),
+        ("workgroups", ctypes.c_uint32),
+        ("order", ctypes.c_int32),
+        ("pairs", ctypes.c_uint64),
+        ("device_bytes", ctypes.c_size_t),
+    ]
+
+
+ORDER_LONGEST_FIRST, ORDER_SHARD = 0, 1
+
+
 def make_opts(**kw) -> KnnOpts:
     o = KnnOpts()
     o.struct_size = ctypes.sizeof(KnnOpts)
@@ -73,6 +88,15 @@ _SIGS = {
     "bdg_build_knn_ex": [_p, _u32, _u32, _u32, _p, _p, _p, _p],
     "bdg_build_knn_workspace_size": [_u32, _u32, _u32, _p, _p],
     "bdg_merge_lists": [_p, _p, _u32, _u32, _u32, _u32, _p, _p, _p],
+    "bdg_batch_plan_create": [_p, _u32, _u32, _u32, _p, _p],
+    "bdg_batch_plan_destroy": [_p],
+    "bdg_batch_plan_info": [_p, _p],
+    "bdg_batch_plan_set_order": [_p, ctypes.c_int],
+    "bdg_build_knn_batched_plan": [_p, _p, _p, _p, _p],
+    "bdg_build_knn_batched_graph": [_p, _p, _p, _p, _p],
+    "bdg_build_knn_batched_ex": [_p, _p, _u32, _u32, _u32, _p, _p, _p, _p],
+    "bdg_autotune_build": [_p, _u32, _u32, _u32, _p, _p, _p, _p, _p, _sz],
+    "bdg_autotune_batched": [_p, _p, _p, _p, _p, _p, _sz],
     "bdg_status_string": [ctypes.c_int],
     "bdg_last_error": [],
     "bdg_version": [],
@@ -94,6 +118,7 @@ def lib():
                 fn.argtypes = args
                 fn.restype = ctypes.c_int
             L.bdg_status_string.restype = ctypes.c_char_p
+            L.bdg_batch_plan_destroy.restype = None
             L.bdg_last_error.restype = ctypes.c_char_p
             _lib = L
     return _lib
@@ -191,3 +216,86 @@ def to_numpy_graph(idx, dist):
     """GPU (int32, int16) graph -> host numpy (uint32, uint16)."""
     import numpy as np
     return (idx.cpu().numpy().view(np.uint32), dist.cpu().numpy().view(np.uint16))
+
+
+# ------------------------------------------------------------ many partitions
+
+def _host_offsets(offsets):
+    import numpy as np
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+    return off, ctypes.c_void_p(off.ctypes.data)
+
+
+class BatchPlan:
+    """A plan for building the graphs of many shards in one persistent launch
+    (``bdg_batch_plan_*``). ``offsets`` is a host array of S + 1 row offsets."""
+
+    def __init__(self, offsets, bits: int, K: int, order: int = ORDER_LONGEST_FIRST):
+        off, ptr = _host_offsets(offsets)
+        self.offsets, self.bits, self.K = off, bits, K
+        self.S = off.size - 1
+        h = ctypes.c_void_p()
+        o = make_opts(tile_variant=order)
+        _check(lib().bdg_batch_plan_create(ptr, self.S, bits, K, ctypes.byref(o), ctypes.byref(h)))
+        self.handle = h
+
+    def info(self) -> BatchInfo:
+        i = BatchInfo()
+        _check(lib().bdg_batch_plan_info(self.handle, ctypes.byref(i)))
+        return i
+
+    def set_order(self, order: int):
+        _check(lib().bdg_batch_plan_set_order(self.handle, order))
+
+    def outputs(self, device="cuda"):
+        import torch
+        n = int(self.offsets[-1])
+        return (torch.empty((n, self.K), dtype=torch.int32, device=device),
+                torch.empty((n, self.K), dtype=torch.int16, device=device))
+
+    def build(self, codes, out=None, stream=None, graph: bool = False):
+        """Enqueue the build (through a HIP graph if ``graph``); returns (idx, dist)."""
+        out = out if out is not None else self.outputs(codes.device)
+        fn = lib().bdg_build_knn_batched_graph if graph else lib().bdg_build_knn_batched_plan
+        _check(fn(self.handle, _ptr(codes), _ptr(out[0]), _ptr(out[1]), _stream(stream)))
+        return out
+
+    def autotune(self, codes, out=None, stream=None) -> str:
+        out = out if out is not None else self.outputs(codes.device)
+        rep = ctypes.create_string_buffer(4096)
+        _check(lib().bdg_autotune_batched(self.handle, _ptr(codes), _ptr(out[0]), _ptr(out[1]),
+                                          _stream(stream), rep, len(rep)))
+        return rep.value.decode()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().bdg_batch_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def bdg_build_knn_batched_ex(codes, offsets, S, bits, K, out_idx, out_dist, opts=None,
+                             stream=None) -> int:
+    off, ptr = _host_offsets(offsets)
+    op = ctypes.byref(opts) if opts is not None else None
+    return lib().bdg_build_knn_batched_ex(_ptr(codes), ptr, S, bits, K, _ptr(out_idx),
+                                          _ptr(out_dist), op, _stream(stream))
+
+
+def autotune_build(codes, K: int, bits: int | None = None, row_block: int = 0, stream=None):
+    """Tune the single-partition schedule; returns (opts, report_json)."""
+    import torch
+    n, words = codes.shape
+    bits = bits or 64 * words
+    out = (torch.empty((n, K), dtype=torch.int32, device=codes.device),
+           torch.empty((n, K), dtype=torch.int16, device=codes.device))
+    o = make_opts(row_block=row_block)
+    rep = ctypes.create_string_buffer(4096)
+    _check(lib().bdg_autotune_build(_ptr(codes), n, bits, K, _ptr(out[0]), _ptr(out[1]),
+                                    ctypes.byref(o), _stream(stream), rep, len(rep)))
+    return o, rep.value.decode()

@@ -18,6 +18,10 @@
 #include "bdg.h"
 #include "kernels.h"
 
+namespace bdg {
+bool tuned_schedule(uint32_t n, uint32_t bits, uint32_t K, int* path, uint32_t* col_block);
+}  // namespace bdg
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -74,6 +78,11 @@ int make_plan(uint32_t n, uint32_t bits, uint32_t K, const bdg_knn_opts* opts, P
   p->K = K;
   p->n = n;
   int path = opts ? opts->path : BDG_PATH_AUTO;
+  uint32_t tuned_cb = 0;
+  if (path == BDG_PATH_AUTO && !(opts && opts->col_block)) {
+    int tp = 0;
+    if (bdg::tuned_schedule(n, bits, K, &tp, &tuned_cb)) path = tp;
+  }
   if (path == BDG_PATH_AUTO) path = path_auto(n, p->words, K);
   if (path != BDG_PATH_POPC && path != BDG_PATH_MFMA)
     return set_error(BDG_EINVAL, "unknown path %d", path);
@@ -83,7 +92,8 @@ int make_plan(uint32_t n, uint32_t bits, uint32_t K, const bdg_knn_opts* opts, P
     return set_error(BDG_EUNSUPPORTED, "path %d does not support n=%u bits=%u K=%u", path, n,
                      bits, K);
   p->path = path;
-  uint32_t cb = (opts && opts->col_block) ? opts->col_block : kDefaultBlock;
+  uint32_t cb = (opts && opts->col_block) ? opts->col_block
+                                          : (tuned_cb ? tuned_cb : kDefaultBlock);
   uint32_t rb = (opts && opts->row_block) ? opts->row_block : kDefaultBlock;
   if (cb > kMaxColBlock)
     return set_error(BDG_EUNSUPPORTED, "col_block > %u", kMaxColBlock);
@@ -113,6 +123,21 @@ int make_plan(uint32_t n, uint32_t bits, uint32_t K, const bdg_knn_opts* opts, P
 }
 
 }  // namespace
+
+namespace bdg {
+// Error reporting for the other host files of the library.
+int api_error(int status, const char* fmt, ...) {
+  char msg[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(msg, sizeof msg, fmt, ap);
+  va_end(ap);
+  g_last_error = msg;
+  return status;
+}
+int api_device_error(hipError_t e, const char* what) { return device_error(e, what); }
+void api_clear_error() { g_last_error.clear(); }
+}  // namespace bdg
 
 extern "C" {
 

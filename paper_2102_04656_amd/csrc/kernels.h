@@ -58,4 +58,23 @@ hipError_t launch_prep(const uint64_t* codes, uint32_t n, uint32_t words, void* 
                        hipStream_t stream);
 hipError_t launch_mfma_run(const RunArgs& a, hipStream_t stream);
 
+// Batched partitions (one persistent launch): work item = up to
+// run_rows_per_wg(K) rows [row0, row0 + nrows) of the shard holding columns
+// [lo, hi); output indices are shard-local (column - lo).
+struct BatchItem {
+  uint32_t row0, nrows, lo, hi;
+};
+struct BatchArgs {
+  const uint64_t* codes;
+  const void* frags;
+  uint32_t words, bits, K, idx_bits;
+  const BatchItem* items;  // device, nitems entries
+  uint32_t nitems;
+  uint32_t* counter;       // device scratch word (reset by the launch)
+  uint32_t grid;           // persistent work-groups
+  uint32_t* out_idx;
+  uint16_t* out_dist;
+};
+hipError_t launch_mfma_batched(const BatchArgs& a, hipStream_t stream);
+
 }  // namespace bdg

@@ -37,41 +37,10 @@
 #include <stdint.h>
 
 #include "kernels.h"
-#include "wave_topk.h"
+#include "tile_mfma_kern.h"
 
 namespace bdg {
-
-namespace {
-
-typedef int v4i __attribute__((ext_vector_type(4)));
-typedef __attribute__((address_space(3))) void lds_void;
-
-constexpr int kWaves = 4;      // waves per work-group
-constexpr int kBuf = 32;       // pending keys per query
-constexpr int kGroupKeys = 16; // keys one query can gain from one 16-code group
-
-// 4 bits -> 4 bytes in {0, 1}: byte t = bit t. The multiplier places copies
-// of the nibble at bit offsets 0, 7, 14, 21 (no two terms overlap), so bit t
-// of the nibble lands at bit 8t.
-__device__ __forceinline__ uint32_t spread_nibble(uint32_t nib) {
-  return (nib * 0x00204081u) & 0x01010101u;
-}
-
-// 16 code bits -> 16 bytes of +-1 (0x01 for a set bit, 0xFF for a clear one).
-__device__ __forceinline__ v4i expand_pm1(uint32_t h) {
-  v4i r;
-#pragma unroll
-  for (int t = 0; t < 4; ++t)
-    r[t] = (int)((spread_nibble((h >> (4 * t)) & 15u) * 0xFEu) ^ 0xFFFFFFFFu);
-  return r;
-}
-
-// Operand bytes of code `row`, word s, lane quarter kq.
-__device__ __forceinline__ v4i code_chunk_pm1(const uint64_t* codes, uint32_t W, uint32_t row,
-                                              uint32_t s, uint32_t kq) {
-  const uint64_t w = codes[(size_t)row * W + s];
-  return expand_pm1((uint32_t)(w >> (16 * kq)) & 0xFFFFu);
-}
+namespace mfma {
 
 // One thread per 16-byte operand chunk; rows >= n are zero (a zero operand
 // gives dot 0; such columns are never admitted by the column-range test).
@@ -89,430 +58,7 @@ __global__ __launch_bounds__(256) void prep_pm1_kernel(const uint64_t* __restric
   frags[t] = v;
 }
 
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Work-group barrier for the stage ring. It emits no memory wait: each
-// thread has already waited for its own stage copies (explicit vm-counter
-// wait), and the reads of the buffer about to be overwritten have completed
-// (their data fed the matrix cores). The signal fences keep the compiler
-// from moving LDS accesses across the barrier.
-__device__ __forceinline__ void lds_barrier() {
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __builtin_amdgcn_s_barrier();
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
-
-// s_waitcnt that waits for at most n outstanding vector-memory operations and
-// nothing else (gfx9 encoding: vmcnt in bits 3:0 and 15:14).
-#define BDG_WAIT_VMCNT(n) \
-  __builtin_amdgcn_s_waitcnt(((n) & 15) | (((n) >> 4) << 14) | (7 << 4) | (15 << 8))
-
-// One 16-byte-per-lane copy from global memory straight into LDS: lane l's
-// 16 bytes land at LDS address lds + 16 l (lds is wave-uniform, in M0). It is
-// written as inline assembly so that the compiler does not track it: its
-// completion is waited for explicitly (vector-memory counter) and published
-// to the other waves through the stage ring below. The instruction has no
-// register destination.
-__device__ __forceinline__ void dma16(const void* gptr, uint32_t lds) {
-  asm volatile(
-      "s_mov_b32 m0, %1\n\t"
-      "s_nop 0\n\t"
-      "global_load_lds_dwordx4 %0, off"
-      :
-      : "v"(gptr), "s"(lds)
-      : "memory", "m0");
-}
-
-__device__ __forceinline__ uint32_t lds_addr(const void* p) {
-  return (uint32_t)(uintptr_t)(const lds_void*)p;
-}
-
-// Copy one stage (SV4 16-byte chunks, contiguous in HBM) into LDS with the
-// whole work-group: every thread issues (SV4 + 255) / 256 copies (a thread
-// past the end repeats a chunk of the previous round: the same bytes to the
-// same place).
-template <int SV4>
-__device__ __forceinline__ void load_stage(const v4i* __restrict__ src, v4i* dst, uint32_t tid) {
-  constexpr int LPS = (SV4 + 255) / 256;
-#pragma unroll
-  for (int i = 0; i < LPS; ++i) {
-    uint32_t v = i * 256 + tid;
-    if (SV4 % 256 != 0 && v >= (uint32_t)SV4) v -= 256;
-    dma16(src + v, __builtin_amdgcn_readfirstlane(lds_addr(dst + (v & ~63u))));
-  }
-}
-
-// Copy one whole stage (SV4 16-byte chunks) with one wave.
-template <int SV4>
-__device__ __forceinline__ void load_stage_wave(const v4i* __restrict__ src, v4i* dst,
-                                                uint32_t lane) {
-  static_assert(SV4 % 64 == 0, "stage is whole wave copies");
-  const uint32_t base = __builtin_amdgcn_readfirstlane(lds_addr(dst));
-#pragma unroll
-  for (int i = 0; i < SV4 / 64; ++i) dma16(src + i * 64 + lane, base + i * 1024);
-}
-
-// Pending keys of one query: 4 sub-buffers of kSub slots, sub-buffer t owned
-// by the lane of lane quarter t that holds the query in the MFMA output
-// (lanes i, i + 16, i + 32, i + 48 for query i of a 16-query group), so a lane
-// appends without coordinating with the others. cq[t] = keys in sub-buffer t.
-constexpr int kSub = kBuf / 4;
-
-// Merge the pending keys of one query into its list; returns the new bias
-// 2 thr - bits of that query (thr = distance of the K-th key, or bits + 1
-// while the list is not full).
-template <int NR>
-__device__ __forceinline__ int flush_sub(uint32_t* list_q, const uint32_t* buf_q,
-                                         uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                         uint32_t K, uint32_t lane, uint32_t IB, uint32_t bits) {
-  const uint32_t t = lane >> 3;
-  const uint32_t ct = t == 0 ? c0 : (t == 1 ? c1 : (t == 2 ? c2 : c3));
-  const uint32_t x = (lane < (uint32_t)kBuf && (lane & (kSub - 1)) < ct) ? buf_q[lane] : kKeyNone;
-  const uint32_t kth = merge_into_list<NR>(list_q, x, K, lane);
-  return kth == kKeyNone ? (int)bits + 2 : 2 * (int)(kth >> IB) - (int)bits;
-}
-
-template <int W, int NR, int QG, int GPS, int NST>
-__global__ __launch_bounds__(256, 1) void knn_mfma_run_kernel(
-    const v4i* __restrict__ frags, const uint64_t* __restrict__ codes, uint32_t K, uint32_t bits,
-    uint32_t IB, uint32_t row0, uint32_t nrows, uint32_t cb, uint32_t ce, int fresh,
-    uint32_t* __restrict__ out_idx, uint16_t* __restrict__ out_dist) {
-  constexpr int QW = 16 * QG;        // queries per wave
-  constexpr int CT = 16 * GPS;       // codes per stage
-  constexpr int SV4 = GPS * W * 64;  // 16-byte chunks per stage
-  constexpr int LPS = (SV4 + 255) / 256;
-  constexpr int kBufW = QW * kBuf + 64;  // + a discard slot per lane
-  __shared__ v4i stage[NST][SV4];
-  extern __shared__ uint32_t state[];
-  uint32_t* lists = state;                    // [kWaves][QW][K]
-  uint32_t* bufs = lists + kWaves * QW * K;   // [kWaves][kBufW]
-
-  const uint32_t tid = threadIdx.x;
-  const uint32_t lane = tid & 63u;
-  const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
-  const uint32_t i16 = lane & 15u;
-  const uint32_t kq = lane >> 4;
-  uint32_t* list_w = lists + wave * QW * K;
-  uint32_t* buf_w = bufs + wave * kBufW;
-  const uint32_t discard = QW * kBuf + lane;
-  const uint32_t q0 = blockIdx.x * (kWaves * QW) + wave * QW;  // first local row of the wave
-  const uint32_t imask = (1u << IB) - 1u;
-  const uint32_t qlo = row0 + q0, qhi = row0 + q0 + QW;  // the wave's rows (as columns)
-
-  const uint32_t cstart = cb & ~15u;
-  const uint32_t nst = (ce - cstart + CT - 1) / CT;
-  const v4i* src0 = frags + (size_t)(cstart / 16) * W * 64;
-  // Stage ring control. The waves move through the stages independently (a
-  // wave that merges lists does not hold the others back), within the slack
-  // the ring allows: landed[b] = 1 + generation of the last stage whose copy
-  // into slot b completed; freed[b] counts the (wave, stage) pairs done
-  // reading slot b; claimed = next stage to be copied. The first wave to
-  // reach a stage start claims the copy of the stage NST - 1 ahead, issues it
-  // (the whole stage) once every wave has finished the slot's previous stage,
-  // and publishes it at its next stage start.
-  __shared__ uint32_t ring_landed[NST], ring_freed[NST], ring_claimed;
-  if (tid < NST) {
-    ring_landed[tid] = tid < NST - 1 ? 1u : 0u;  // stages 0..NST-2: the prologue copies
-    ring_freed[tid] = 0;
-  }
-  if (tid == 0) ring_claimed = NST - 1;
-#pragma unroll
-  for (int p = 0; p < NST - 1; ++p)
-    if ((uint32_t)p < nst) load_stage<SV4>(src0 + (size_t)p * SV4, stage[p], tid);
-
-  // Running lists of the wave's rows (the output rows hold the merge of the
-  // earlier column blocks unless this is the first).
-  for (uint32_t p = lane; p < (uint32_t)(QW * K); p += kWave) {
-    const uint32_t q = p / K;
-    uint32_t key = kKeyNone;
-    if (!fresh && q0 + q < nrows) {
-      const size_t o = (size_t)(q0 + q) * K + (p - q * K);
-      const uint32_t j = out_idx[o];
-      if (j != 0xFFFFFFFFu) key = ((uint32_t)out_dist[o] << IB) | j;
-    }
-    list_w[p] = key;
-  }
-  wave_sync();
-
-  v4i bq[QG][W];
-  v4i biasC[QG];
-  uint32_t qrow[QG], csub[QG];
-#pragma unroll
-  for (int gq = 0; gq < QG; ++gq) {
-    const uint32_t ql = q0 + 16 * gq + i16;
-    const bool valid = ql < nrows;
-    const uint32_t row = row0 + (valid ? ql : 0u);
-#pragma unroll
-    for (int s = 0; s < W; ++s) bq[gq][s] = code_chunk_pm1(codes, W, row, s, kq);
-    int bias = -(int)bits;  // absent row: acc = dot - bits <= 0, never passes
-    if (valid) {
-      const uint32_t kth = list_w[(16 * gq + i16) * K + K - 1];
-      bias = kth == kKeyNone ? (int)bits + 2 : 2 * (int)(kth >> IB) - (int)bits;
-    }
-    biasC[gq] = v4i{bias, bias, bias, bias};
-    qrow[gq] = row0 + ql;
-    csub[gq] = 0;
-  }
-
-  BDG_WAIT_VMCNT(0);  // prologue stage copies (all threads) and ring init
-  __syncthreads();
-
-  // Flush every query of group gq whose lanes are flagged in m (a ballot).
-  auto flush_group = [&](const int gq, uint64_t m) {
-    uint32_t qm = (uint32_t)(m | (m >> 16) | (m >> 32) | (m >> 48)) & 0xFFFFu;
-    wave_sync();
-    while (qm) {
-      const uint32_t i = __builtin_ctz(qm);
-      qm &= qm - 1;
-      const uint32_t qi = 16 * gq + i;
-      const int bias = flush_sub<NR>(
-          list_w + qi * K, buf_w + qi * kBuf, __builtin_amdgcn_readlane(csub[gq], i),
-          __builtin_amdgcn_readlane(csub[gq], 16 + i), __builtin_amdgcn_readlane(csub[gq], 32 + i),
-          __builtin_amdgcn_readlane(csub[gq], 48 + i), K, lane, IB, bits);
-      if (i16 == i) {
-        biasC[gq] = v4i{bias, bias, bias, bias};
-        csub[gq] = 0;
-      }
-      wave_sync();
-    }
-  };
-
-  // Filter of the 16-code group starting at column cs, contracted with the
-  // biases bb - bits: append every candidate that beat its query's threshold.
-  auto maxacc = [&](const v4i (&acc)[QG]) {
-    int mx = acc[0][0];
-#pragma unroll
-    for (int gq = 0; gq < QG; ++gq)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) mx = max(mx, acc[gq][r]);
-    return mx;
-  };
-  auto append = [&](const v4i (&acc)[QG], const int (&bb)[QG], const uint32_t cs) {
-    const uint32_t c0 = cs + 4 * kq;
-    const bool edge = cs < cb || cs + 16 > ce;   // group crosses the column range
-    const bool diag = cs < qhi && cs + 16 > qlo;  // group holds some of the wave's rows
-#pragma unroll
-    for (int gq = 0; gq < QG; ++gq) {
-      const int m4 = max(max(acc[gq][0], acc[gq][1]), max(acc[gq][2], acc[gq][3]));
-      if (!__any(m4 > 0)) continue;
-      // Pass flags as sign bits: p_r = 1 iff acc_r > lim_r. lim_r = 0, except
-      // (in the few groups on the column-range edge or holding the wave's own
-      // rows) a column outside [cb, ce) or the query's own row never passes.
-      int lim[4] = {0, 0, 0, 0};
-      if (edge || diag) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const uint32_t col = c0 + r;
-          lim[r] = (col < cb || col >= ce || col == qrow[gq]) ? 0x7FFFFFFF : 0;
-        }
-      }
-      uint32_t pass[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) pass[r] = (uint32_t)(lim[r] - acc[gq][r]) >> 31;
-      const uint32_t c = pass[0] + pass[1] + pass[2] + pass[3];
-      const uint64_t over = __ballot(csub[gq] + c > (uint32_t)kSub);
-      if (over) flush_group(gq, over);
-      uint32_t pos = (16 * gq + i16) * kBuf + kq * kSub + csub[gq];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        // (bb - acc) = 2 ham, so this is ham << IB | column
-        const uint32_t key = ((uint32_t)(bb[gq] - acc[gq][r]) << (IB - 1)) | (c0 + r);
-        buf_w[pass[r] ? pos : discard] = key;
-        pos += pass[r];
-      }
-      csub[gq] += c;
-    }
-  };
-
-  auto issue = [&](v4i (&acc)[QG], int (&bb)[QG], const v4i (&a)[W]) {
-#pragma unroll
-    for (int s = 0; s < W; ++s)
-#pragma unroll
-      for (int gq = 0; gq < QG; ++gq)
-        acc[gq] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[s], bq[gq][s],
-                                                        s == 0 ? biasC[gq] : acc[gq], 0, 0, 0);
-#pragma unroll
-    for (int gq = 0; gq < QG; ++gq) bb[gq] = biasC[gq][0] + (int)bits;
-  };
-
-  // Per stage: the contraction of group g is issued before the filter of
-  // group g - 1 (ping-pong accumulators), so the matrix cores keep busy while
-  // the vector ALUs test. A group contracted before a merge tightened a
-  // threshold just admits a superset; its keys use the bias it was contracted
-  // with. The operand reads of group g + 1 are pinned ahead of group g's
-  // contraction, and the test of group g - 1 is interleaved with it.
-  constexpr int kTestOps = 2 * QG;  // vector ops of the max-reduction, about
-  auto issue_and_test = [&](v4i (&accN)[QG], int (&bbN)[QG], const v4i (&a)[W],
-                            const v4i (&accP)[QG]) {
-    issue(accN, bbN, a);
-    const int mx = maxacc(accP);
-#pragma unroll
-    for (int i = 0; i < kTestOps && i < W * QG; ++i) {
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
-      __builtin_amdgcn_sched_group_barrier(0x002, 1, 0);  // one vector op
-    }
-    __builtin_amdgcn_sched_group_barrier(0x008, W * QG, 0);
-    return mx;
-  };
-
-  v4i acc[2][QG];
-  int bb[2][QG];
-  uint32_t pend = 0xFFFFFFFFu;  // stage this wave copies and has not published
-#pragma unroll 1
-  for (uint32_t st = 0; st < nst; ++st) {
-    const uint32_t slot = st % NST;
-    if (pend != 0xFFFFFFFFu) {  // publish the copy issued one stage ago
-      BDG_WAIT_VMCNT(0);
-      __atomic_signal_fence(__ATOMIC_SEQ_CST);
-      if (lane == 0)
-        __hip_atomic_store(&ring_landed[pend % NST], pend / NST + 1, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_WORKGROUP);
-      pend = 0xFFFFFFFFu;
-    }
-    while (__hip_atomic_load(&ring_landed[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <
-           st / NST + 1)
-      __builtin_amdgcn_s_sleep(1);
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    const uint32_t t = st + NST - 1;
-    if (t < nst && __hip_atomic_load(&ring_claimed, __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_WORKGROUP) == t) {
-      uint32_t won = 0;
-      if (lane == 0) {
-        uint32_t expect = t;
-        won = __hip_atomic_compare_exchange_strong(&ring_claimed, &expect, t + 1,
-                                                   __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_WORKGROUP)
-                  ? 1u
-                  : 0u;
-      }
-      if (__builtin_amdgcn_readfirstlane(won)) {
-        if (t >= (uint32_t)NST)
-          while (__hip_atomic_load(&ring_freed[t % NST], __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP) < kWaves * (t / NST))
-            __builtin_amdgcn_s_sleep(1);
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        load_stage_wave<SV4>(src0 + (size_t)t * SV4, stage[t % NST], lane);
-        pend = t;
-      }
-    }
-    const v4i* sb = stage[slot];
-    const uint32_t cs0 = cstart + st * CT;
-    v4i a[2][W];  // operands of groups g and g + 1 (read one group ahead)
-#pragma unroll
-    for (int s = 0; s < W; ++s) a[0][s] = sb[s * 64 + lane];
-    if (GPS % 2 == 0 && st > 0) {  // last group of stage st - 1
-      if (__any(maxacc(acc[1]) > 0)) append(acc[1], bb[1], cs0 - 16);
-    }
-#pragma unroll
-    for (int g = 0; g < GPS; ++g) {
-      if (g + 1 < GPS) {
-#pragma unroll
-        for (int s = 0; s < W; ++s) a[(g + 1) & 1][s] = sb[((g + 1) * W + s) * 64 + lane];
-      }
-      if (g + 1 == GPS) {
-        // every operand of the stage is in registers: the slot can be reused
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        if (lane == 0)
-          __hip_atomic_fetch_add(&ring_freed[slot], 1u, __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_WORKGROUP);
-      }
-      __builtin_amdgcn_sched_barrier(0);
-      if (g > 0) {
-        const int mx = issue_and_test(acc[g & 1], bb[g & 1], a[g & 1], acc[(g - 1) & 1]);
-        if (__any(mx > 0)) append(acc[(g - 1) & 1], bb[(g - 1) & 1], cs0 + 16 * (g - 1));
-      } else {
-        issue(acc[0], bb[0], a[0]);
-      }
-    }
-    if (GPS % 2 != 0) {
-      if (__any(maxacc(acc[(GPS - 1) & 1]) > 0))
-        append(acc[(GPS - 1) & 1], bb[(GPS - 1) & 1], cs0 + 16 * (GPS - 1));
-    }
-  }
-  if (GPS % 2 == 0 && nst > 0) {
-    if (__any(maxacc(acc[1]) > 0)) append(acc[1], bb[1], cstart + nst * CT - 16);
-  }
-  BDG_WAIT_VMCNT(0);  // no stage copy of this wave is still in flight
-
-  // Pending keys, then the lists back to the output rows.
-#pragma unroll
-  for (int gq = 0; gq < QG; ++gq) {
-    const uint64_t m = __ballot(csub[gq] > 0);
-    if (m) flush_group(gq, m);
-  }
-  for (uint32_t p = lane; p < (uint32_t)(QW * K); p += kWave) {
-    const uint32_t q = p / K;
-    if (q0 + q >= nrows) break;
-    const uint32_t key = list_w[p];
-    const size_t o = (size_t)(q0 + q) * K + (p - q * K);
-    out_idx[o] = key == kKeyNone ? 0xFFFFFFFFu : (key & imask);
-    out_dist[o] = key == kKeyNone ? (uint16_t)0xFFFFu : (uint16_t)(key >> IB);
-  }
-}
-
-// Launch shape per (W, list size). 16-code groups per stage: up to 4 (the
-// operands per stage, with the per-thread load count kept whole.
-template <int W>
-constexpr int stage_groups() {
-  return W <= 5 ? 4 : (W <= 8 ? 2 : 1);
-}
-// Queries per wave / 16 and stage buffers, so that lists, buffers and stages
-// fit the 160 KB of LDS of a CU (one work-group per CU).
-template <int NR>
-constexpr int run_qgroups() {
-  return NR == 1 ? 4 : (NR == 2 ? 3 : 1);
-}
-template <int NR>
-constexpr int run_stages() {
-  return NR == 2 ? 2 : 3;
-}
-
-int nr_of(uint32_t K) { return K <= 64 ? 1 : (K <= 128 ? 2 : 4); }
-int qg_of(uint32_t K) { return nr_of(K) == 1 ? 4 : (nr_of(K) == 2 ? 3 : 1); }
-int nst_of(uint32_t K) { return nr_of(K) == 2 ? 2 : 3; }
-
-uint32_t groups_of(uint32_t W) { return W <= 5 ? 4u : (W <= 8 ? 2u : 1u); }
-
-size_t run_state_bytes(uint32_t K, int qg) {
-  const size_t qw = 16u * qg;
-  return (size_t)kWaves * (qw * K + qw * kBuf + 64) * 4;
-}
-
-size_t run_lds_bytes(uint32_t W, uint32_t K) {
-  const size_t stage = (size_t)groups_of(W) * W * 1024;
-  return nst_of(K) * stage + run_state_bytes(K, qg_of(K));
-}
-
-template <int W, int NR>
-hipError_t launch_run_w(const RunArgs& a, hipStream_t stream) {
-  constexpr int QG = run_qgroups<NR>();
-  auto kern = knn_mfma_run_kernel<W, NR, QG, stage_groups<W>(), run_stages<NR>()>;
-  const size_t lds = run_state_bytes(a.K, QG);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  const uint32_t rows_per_wg = kWaves * 16 * QG;
-  dim3 grid((a.nrows + rows_per_wg - 1) / rows_per_wg);
-  hipLaunchKernelGGL(kern, grid, dim3(256), lds, stream,
-                     reinterpret_cast<const v4i*>(a.frags), a.codes, a.K, a.bits, a.idx_bits,
-                     a.row0, a.nrows, a.cb, a.ce, a.fresh, a.out_idx, a.out_dist);
-  return hipGetLastError();
-}
-
-template <int W>
-hipError_t launch_run_nr(const RunArgs& a, hipStream_t stream) {
-  switch (nr_of(a.K)) {
-    case 1: return launch_run_w<W, 1>(a, stream);
-    case 2: return launch_run_w<W, 2>(a, stream);
-    default: return launch_run_w<W, 4>(a, stream);
-  }
-}
-
-}  // namespace
+}  // namespace mfma
 
 uint32_t run_idx_bits(uint32_t bits) {
   uint32_t need = 0;
@@ -523,7 +69,7 @@ uint32_t run_idx_bits(uint32_t bits) {
 bool run_supported(uint32_t n, uint32_t words, uint32_t K) {
   if (words < 1 || words > 16 || K < 1 || K > 256) return false;
   if ((uint64_t)n > (1ull << run_idx_bits(64 * words)) - 1) return false;
-  return run_lds_bytes(words, K) <= 160 * 1024;
+  return mfma::run_lds_bytes(words, K) <= 160 * 1024;
 }
 
 size_t prep_rows(uint32_t n) {
@@ -536,32 +82,55 @@ hipError_t launch_prep(const uint64_t* codes, uint32_t n, uint32_t words, void* 
                        hipStream_t stream) {
   const size_t chunks = prep_rows(n) * words * 4;
   dim3 grid((unsigned)((chunks + 255) / 256));
-  hipLaunchKernelGGL(prep_pm1_kernel, grid, dim3(256), 0, stream, codes, n, words, chunks,
-                     reinterpret_cast<v4i*>(frags));
+  hipLaunchKernelGGL(mfma::prep_pm1_kernel, grid, dim3(256), 0, stream, codes, n, words, chunks,
+                     reinterpret_cast<mfma::v4i*>(frags));
   return hipGetLastError();
 }
 
-uint32_t run_rows_per_wg(uint32_t K) { return kWaves * 16u * qg_of(K); }
+uint32_t run_rows_per_wg(uint32_t K) { return mfma::kWaves * 16u * mfma::qg_of(K); }
+
+hipError_t launch_mfma_batched(const BatchArgs& a, hipStream_t stream) {
+  if (a.nitems == 0) return hipSuccess;
+  switch (a.words) {
+    case 1: return mfma::launch_batched_words<1>(a, stream);
+    case 2: return mfma::launch_batched_words<2>(a, stream);
+    case 3: return mfma::launch_batched_words<3>(a, stream);
+    case 4: return mfma::launch_batched_words<4>(a, stream);
+    case 5: return mfma::launch_batched_words<5>(a, stream);
+    case 6: return mfma::launch_batched_words<6>(a, stream);
+    case 7: return mfma::launch_batched_words<7>(a, stream);
+    case 8: return mfma::launch_batched_words<8>(a, stream);
+    case 9: return mfma::launch_batched_words<9>(a, stream);
+    case 10: return mfma::launch_batched_words<10>(a, stream);
+    case 11: return mfma::launch_batched_words<11>(a, stream);
+    case 12: return mfma::launch_batched_words<12>(a, stream);
+    case 13: return mfma::launch_batched_words<13>(a, stream);
+    case 14: return mfma::launch_batched_words<14>(a, stream);
+    case 15: return mfma::launch_batched_words<15>(a, stream);
+    case 16: return mfma::launch_batched_words<16>(a, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_mfma_run(const RunArgs& a, hipStream_t stream) {
   if (a.nrows == 0 || a.ce <= a.cb) return hipSuccess;
   switch (a.words) {
-    case 1: return launch_run_nr<1>(a, stream);
-    case 2: return launch_run_nr<2>(a, stream);
-    case 3: return launch_run_nr<3>(a, stream);
-    case 4: return launch_run_nr<4>(a, stream);
-    case 5: return launch_run_nr<5>(a, stream);
-    case 6: return launch_run_nr<6>(a, stream);
-    case 7: return launch_run_nr<7>(a, stream);
-    case 8: return launch_run_nr<8>(a, stream);
-    case 9: return launch_run_nr<9>(a, stream);
-    case 10: return launch_run_nr<10>(a, stream);
-    case 11: return launch_run_nr<11>(a, stream);
-    case 12: return launch_run_nr<12>(a, stream);
-    case 13: return launch_run_nr<13>(a, stream);
-    case 14: return launch_run_nr<14>(a, stream);
-    case 15: return launch_run_nr<15>(a, stream);
-    case 16: return launch_run_nr<16>(a, stream);
+    case 1: return mfma::launch_run_words<1>(a, stream);
+    case 2: return mfma::launch_run_words<2>(a, stream);
+    case 3: return mfma::launch_run_words<3>(a, stream);
+    case 4: return mfma::launch_run_words<4>(a, stream);
+    case 5: return mfma::launch_run_words<5>(a, stream);
+    case 6: return mfma::launch_run_words<6>(a, stream);
+    case 7: return mfma::launch_run_words<7>(a, stream);
+    case 8: return mfma::launch_run_words<8>(a, stream);
+    case 9: return mfma::launch_run_words<9>(a, stream);
+    case 10: return mfma::launch_run_words<10>(a, stream);
+    case 11: return mfma::launch_run_words<11>(a, stream);
+    case 12: return mfma::launch_run_words<12>(a, stream);
+    case 13: return mfma::launch_run_words<13>(a, stream);
+    case 14: return mfma::launch_run_words<14>(a, stream);
+    case 15: return mfma::launch_run_words<15>(a, stream);
+    case 16: return mfma::launch_run_words<16>(a, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -77,12 +77,46 @@ def test_empty_input_is_a_noop():
 
 
 def test_workspace_size():
-    # one column block: no workspace; several: L * row_block * K * (4 + 2) bytes, aligned
-    assert bdg.bdg_build_knn_workspace_size(1000, 256, 8) == 0
-    o = bdg.make_opts(col_block=250, row_block=300)
+    # vector-ALU path: none with one column block; with several, the per-block
+    # lists of one row block: L * row_block * K * (4 + 2) bytes, each part aligned
+    popc = bdg.PATH_POPC
+    assert bdg.bdg_build_knn_workspace_size(1000, 256, 8, bdg.make_opts(path=popc)) == 0
+    o = bdg.make_opts(path=popc, col_block=250, row_block=300)
     ws = bdg.bdg_build_knn_workspace_size(1000, 256, 8, o)
     ent = 4 * 300 * 8
     assert ws == ((ent * 4 + 255) // 256) * 256 + ((ent * 2 + 255) // 256) * 256
+    # matrix-core path: the +-1 operand fragments of all codes (bits bytes per row,
+    # rows rounded up to 16 plus 256 rows of slack), whatever the blocking
+    for kw in (dict(), dict(col_block=250, row_block=300)):
+        o = bdg.make_opts(path=bdg.PATH_MFMA, **kw)
+        ws = bdg.bdg_build_knn_workspace_size(1000, 256, 8, o)
+        assert ws == (((1000 + 15) // 16 * 16 + 256) * 256 + 255) // 256 * 256
+
+
+def test_batched_plan_rejects_bad_arguments():
+    import numpy as np
+    L = bdg.lib()
+    h = ctypes.c_void_p()
+    good = np.array([0, 10, 30], dtype=np.uint64)
+    bad = np.array([0, 10, 5], dtype=np.uint64)
+
+    def create(off, S=2, bits=256, K=8):
+        return L.bdg_batch_plan_create(ctypes.c_void_p(off.ctypes.data), S, bits, K, None,
+                                       ctypes.byref(h))
+    assert create(bad) == bdg.BDG_EINVAL                      # decreasing offsets
+    assert create(good, bits=100) == bdg.BDG_EINVAL
+    assert create(good, bits=2048) == bdg.BDG_EUNSUPPORTED
+    assert create(good, K=0) == bdg.BDG_EINVAL
+    assert create(good, K=1000) == bdg.BDG_EUNSUPPORTED
+    huge = np.array([0, 1 << 23], dtype=np.uint64)           # shard beyond the 23-bit index field
+    assert create(huge, S=1) == bdg.BDG_EUNSUPPORTED
+    assert L.bdg_batch_plan_create(None, 2, 256, 8, None, ctypes.byref(h)) == bdg.BDG_EINVAL
+    assert L.bdg_batch_plan_create(ctypes.c_void_p(good.ctypes.data), 2, 256, 8, None,
+                                   None) == bdg.BDG_EINVAL
+    assert L.bdg_build_knn_batched_plan(None, FAKE, FAKE, FAKE, None) == bdg.BDG_EINVAL
+    assert L.bdg_build_knn_batched_graph(None, FAKE, FAKE, FAKE, FAKE) == bdg.BDG_EINVAL
+    assert L.bdg_autotune_batched(None, FAKE, FAKE, FAKE, None, None, 0) == bdg.BDG_EINVAL
+    assert L.bdg_autotune_build(FAKE, 10, 256, 8, FAKE, FAKE, None, None, None, 0) == bdg.BDG_EINVAL
 
 
 def test_merge_rejects_bad_arguments():

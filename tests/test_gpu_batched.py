@@ -1,0 +1,167 @@
+"""GPU parity of the batched build (many shards in one persistent launch) and of
+the autotuner: every shard's graph, with shard-local indices, equals the CPU
+oracle on that shard alone, bit for bit; work orders, HIP-graph replays and
+tuned schedules give the same graph.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2102_04656_amd import bdg, datagen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    bdg.lib()
+
+
+def dev(codes):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(codes).view(np.int64)).cuda()
+
+
+def to_np(out):
+    import torch
+    torch.cuda.synchronize()
+    return bdg.to_numpy_graph(*out)
+
+
+def shard_codes(sizes, bits, seed, p=0.2):
+    """Concatenated shards, each from its own few centres."""
+    g = np.random.default_rng(seed)
+    parts = [datagen.clustered_codes(int(n), bits, n_centres=max(1, int(n) // 50 + 1), p=p,
+                                     seed=int(g.integers(1 << 30))) if n else
+             np.zeros((0, bits // 64), dtype=np.uint64) for n in sizes]
+    offsets = np.zeros(len(sizes) + 1, dtype=np.uint64)
+    offsets[1:] = np.cumsum(sizes)
+    return np.concatenate(parts), offsets
+
+
+def check_shard(gi, gd, codes, offsets, s, K, rows=None):
+    lo, hi = int(offsets[s]), int(offsets[s + 1])
+    if hi == lo:
+        return
+    want = oracle.knn_rows(codes[lo:hi], K, rows=rows)
+    sel = np.arange(lo, hi) if rows is None else lo + np.asarray(rows)
+    if not (np.array_equal(gi[sel], want[0]) and np.array_equal(gd[sel], want[1])):
+        bad = np.nonzero((gi[sel] != want[0]).any(1) | (gd[sel] != want[1]).any(1))[0]
+        r = int(bad[0])
+        raise AssertionError(f"shard {s} (rows {lo}..{hi}): {bad.size} rows differ; row {r}: "
+                             f"got {list(zip(gd[sel][r][:8], gi[sel][r][:8]))} "
+                             f"want {list(zip(want[1][r][:8], want[0][r][:8]))}")
+
+
+@pytest.mark.parametrize("bits,K", [(256, 32), (128, 7), (512, 100), (192, 64)])
+def test_small_and_ragged_shards(bits, K):
+    # empty, single-row, fewer rows than K, tile edges (255/256/257), and larger shards
+    sizes = [0, 1, 2, 17, 255, 256, 257, 600, 1000, 0, 3001, 40, 5]
+    codes, offsets = shard_codes(sizes, bits, seed=bits + K)
+    plan = bdg.BatchPlan(offsets, bits, K)
+    info = plan.info()
+    assert info.shards == len(sizes) and info.rows == int(offsets[-1])
+    out = plan.build(dev(codes))
+    gi, gd = to_np(out)
+    for s in range(len(sizes)):
+        check_shard(gi, gd, codes, offsets, s, K)
+    plan.close()
+
+
+def test_shard_offsets_need_not_start_at_zero():
+    codes, _ = shard_codes([500, 700], 256, seed=3)
+    offsets = np.array([100, 400, 1200], dtype=np.uint64)  # rows 0..99 belong to no shard
+    import torch
+    plan = bdg.BatchPlan(offsets, 256, 16)
+    out = plan.outputs()
+    out[0].fill_(-5)
+    plan.build(dev(codes), out=out)
+    gi, gd = to_np(out)
+    assert (gi[:100] == np.uint32(0xFFFFFFFB)).all()  # untouched
+    for s in range(2):
+        check_shard(gi, gd, codes, offsets, s, 16)
+
+
+def test_orders_graph_replay_and_autotune_agree():
+    import torch
+    g = np.random.default_rng(7)
+    sizes = np.rint(np.exp(g.uniform(np.log(300), np.log(12000), size=24))).astype(np.int64)
+    codes, offsets = shard_codes(sizes, 256, seed=11)
+    d = dev(codes)
+    plan = bdg.BatchPlan(offsets, 256, 32)
+    ref = to_np(plan.build(d))
+    for s in g.choice(len(sizes), size=6, replace=False):
+        n_s = int(sizes[s])
+        check_shard(*ref, codes, offsets, int(s), 32,
+                    rows=np.unique(np.r_[0, n_s - 1, g.integers(0, n_s, 30)]))
+    plan.set_order(bdg.ORDER_SHARD)
+    got = to_np(plan.build(d))
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+    # captured once, replayed: every replay equals the eager build
+    stream = torch.cuda.Stream()
+    out = plan.outputs()
+    for rep in range(3):
+        out[0].zero_()
+        out[1].zero_()
+        torch.cuda.synchronize()
+        plan.build(d, out=out, stream=stream, graph=True)
+        stream.synchronize()
+        got = to_np(out)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), f"replay {rep}"
+    report = plan.autotune(d)
+    assert '"kind": "batched"' in report
+    got = to_np(plan.build(d))
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+    plan.close()
+
+
+def test_one_shot_entry_point():
+    import torch
+    codes, offsets = shard_codes([900, 50, 2200], 128, seed=5)
+    n = int(offsets[-1])
+    idx = torch.empty((n, 24), dtype=torch.int32, device="cuda")
+    dist = torch.empty((n, 24), dtype=torch.int16, device="cuda")
+    assert bdg.bdg_build_knn_batched_ex(dev(codes), offsets, 3, 128, 24, idx, dist) == 0
+    gi, gd = to_np((idx, dist))
+    for s in range(3):
+        check_shard(gi, gd, codes, offsets, s, 24)
+
+
+def test_sharded_workload_scaled():
+    """The many-shards workload (log-uniform shard sizes, 10-500 centres per
+    shard, 256 bits, flip 0.2, K = 32) at a scale the CPU oracle checks in
+    seconds: 64 shards of 2,000-40,000 rows; every shard on sampled rows, the
+    small ones in full."""
+    codes, offsets = datagen.sharded_codes(n_shards=64, lo=2000, hi=40_000, c_lo=10, c_hi=500,
+                                           bits=256, p=0.2, seed=31)
+    plan = bdg.BatchPlan(offsets, 256, 32)
+    gi, gd = to_np(plan.build(dev(codes)))
+    g = np.random.default_rng(3)
+    sizes = np.diff(offsets.astype(np.int64))
+    for s in range(64):
+        n_s = int(sizes[s])
+        rows = None if n_s <= 2500 else np.unique(np.r_[0, 255, 256, n_s - 1,
+                                                         g.integers(0, n_s, 25)])
+        check_shard(gi, gd, codes, offsets, s, 32, rows=rows)
+    plan.close()
+
+
+def test_autotune_build_keeps_the_graph():
+    import torch
+    codes = datagen.clustered_codes(20_000, 128, 100, 0.15, seed=1)
+    d = dev(codes)
+    want = oracle.knn_rows(codes, 32, rows=np.arange(0, 20_000, 97))
+    opts, report = bdg.autotune_build(d, 32)
+    assert opts.path in (bdg.PATH_MFMA, bdg.PATH_POPC) and opts.col_block > 0
+    assert '"chosen"' in report
+    idx, dist = bdg.build_knn(d, 32, path=opts.path, col_block=opts.col_block)
+    gi, gd = to_np((idx, dist))
+    rows = np.arange(0, 20_000, 97)
+    assert np.array_equal(gi[rows], want[0]) and np.array_equal(gd[rows], want[1])
+    # path AUTO with no explicit column block now takes the tuned schedule: same graph
+    idx2, dist2 = bdg.build_knn(d, 32)
+    g2 = to_np((idx2, dist2))
+    assert np.array_equal(g2[0], gi) and np.array_equal(g2[1], gd)
