@@ -17,7 +17,8 @@ Contents
                              merge-sort of the second reduce, Sec. 3.2 / 3.3).
   * ``knn_sharded_rows``  -- the definition applied per shard, local indices.
   * ``pair_distances``    -- Hamming distance of explicit pairs.
-Floating-point parts of the learned binariser live in ``oracle.learned``.
+Floating-point parts (the binarisers, the float-kNN ground truth, the encoder
+network, its loss and optimiser) live in ``oracle.learned``.
 """
 from __future__ import annotations
 
