@@ -188,6 +188,102 @@ int bdg_build_knn_batched_ex(const uint64_t *codes, const uint64_t *offsets, uin
                              uint32_t bits, uint32_t K, uint32_t *out_idx, uint16_t *out_dist,
                              const bdg_knn_opts *opts, void *stream);
 
+/* ------------------------------------------------ binarisers, float kNN --- */
+
+/*
+ * Sign-of-random-projection codes (the plain binariser; features are mapped
+ * to Hamming space preserving locality, Sec. 3.1): bit j of row i is 1 iff
+ * <x_i, proj[:, j]> > 0 in FP32 (strictly). x: device float [n][d] (d a
+ * multiple of 16), proj: device float [d][bits] (bits a multiple of 64, at
+ * most BDG_MAX_BITS), out_codes: device uint64 [n][bits/64] in the code
+ * layout. Enqueues on `stream`.
+ */
+int bdg_encode(const float *x, uint32_t n, uint32_t d, const float *proj, uint32_t bits,
+               uint64_t *out_codes, void *stream);
+
+/* Codes from real values: bit j of row i = [z[i][j] > 0]; z device float
+ * [n][bits]. */
+int bdg_pack_signs(const float *z, uint32_t n, uint32_t bits, uint64_t *out_codes, void *stream);
+
+/*
+ * Exact squared-L2 kNN in FP32, the real-valued ground truth of recall
+ * (Sec. 4.2): row q = the first K of (||q - y_j||^2, j) over base rows j,
+ * leaving out exclude[q] (device int32 [nq], -1 = none; NULL = none), ties to
+ * the smaller index. Distances are assembled as |q|^2 + |y|^2 - 2 <q, y>
+ * (inner products by a library FP32 GEMM), so near-ties closer than FP32
+ * rounding may order differently from exact arithmetic. queries: device
+ * float [nq][d], base: device float [nb][d]; out_idx uint32 [nq][K] and
+ * out_dist float [nq][K] (padding: 0xFFFFFFFF / +inf). K in 1..128.
+ * Allocates a stream-ordered workspace (about 2 GB at most).
+ */
+int bdg_float_knn(const float *queries, uint32_t nq, const float *base, uint32_t nb, uint32_t d,
+                  uint32_t K, const int32_t *exclude, uint32_t *out_idx, float *out_dist,
+                  void *stream);
+
+/*
+ * The learned binariser: an MLP d -> h -> bits with tanh units,
+ *   Z1 = X W1^T + b1, H1 = tanh Z1, Z2 = H1 W2^T + b2, H = tanh Z2,
+ * code bit j = [Z2_j > 0]. Products run on the BF16 matrix cores with FP32
+ * accumulation; master weights are FP32. All pointers are device memory owned
+ * by the caller. Shapes: d % 32 == 0, h % 64 == 0, bits % 64 == 0 (<= 1024);
+ * a batch holds rows_pad rows (a multiple of 32), of which `rows` are used.
+ */
+typedef struct bdg_mlp_params {
+    uint32_t d, h, bits;
+    float *W1, *b1;          /* [h][d], [h] */
+    float *W2, *b2;          /* [bits][h], [bits] */
+    uint16_t *W1b;           /* bf16 copy of W1, [h][d] (bdg_mlp_refresh) */
+    uint16_t *W2b, *W2bt;    /* bf16 copies of W2, [bits][h] and transposed [h][bits] */
+} bdg_mlp_params;
+
+typedef struct bdg_mlp_acts {
+    uint32_t rows, rows_pad;
+    uint16_t *Xb, *Xt;       /* input, bf16 [rows_pad][d] and [d][rows_pad] (Xt may be NULL
+                                for inference) */
+    float *H1;               /* [rows_pad][h] */
+    uint16_t *H1b, *H1t;     /* bf16 [rows_pad][h] and [h][rows_pad] */
+    float *Z2, *H;           /* [rows_pad][bits] */
+    uint16_t *dZ2b, *dZ2t;   /* bf16 [rows_pad][bits] and [bits][rows_pad] */
+    uint16_t *dZ1t;          /* bf16 [h][rows_pad] */
+} bdg_mlp_acts;
+
+typedef struct bdg_mlp_grads {
+    float *W1, *b1, *W2, *b2; /* shapes of the parameters */
+} bdg_mlp_grads;
+
+typedef struct bdg_loss_opts {
+    float margin, tau, lam_q, lam_b;
+} bdg_loss_opts;
+
+/* Batch rows X[idx[r]] * scale (idx NULL: rows 0..rows-1; 0xFFFFFFFF: a zero
+ * row) into a->Xb / a->Xt; sets a->rows. X: device float [*][d]. */
+int bdg_mlp_gather(const float *X, uint32_t d, const uint32_t *idx, uint32_t rows, float scale,
+                   bdg_mlp_acts *a, void *stream);
+int bdg_mlp_forward(const bdg_mlp_params *p, bdg_mlp_acts *a, void *stream);
+/* Triplet loss on relaxed Hamming distances d(u, v) = (bits - <h_u, h_v>) / 2
+ * of the rows (anchors 0..T-1, positives T..2T-1, negatives 2T..3T-1):
+ *   L = mean softplus((d_ap - d_an + margin) / tau)
+ *       + lam_q mean (|h| - 1)^2 + lam_b sum_j (mean_rows h_j)^2.
+ * Writes dL/dZ2 into a->dZ2b / a->dZ2t (padding rows zero), gb2 = its column
+ * sums, mu [bits] = the column means, *loss (device float) = L. */
+int bdg_triplet_loss(const bdg_mlp_acts *a, uint32_t bits, uint32_t T, const bdg_loss_opts *o,
+                     float *mu, float *gb2, float *loss, void *stream);
+/* Gradients of W2, W1, b1 from a->dZ2b / a->dZ2t (b2's come from the loss). */
+int bdg_mlp_backward(const bdg_mlp_params *p, const bdg_mlp_acts *a, bdg_mlp_grads *g,
+                     void *stream);
+/* Adam with bias correction (step t counts from 1) on `count` floats. */
+int bdg_adam_step(float *param, const float *grad, float *m, float *v, size_t count, uint32_t t,
+                  float lr, float beta1, float beta2, float eps, void *stream);
+/* Refresh the bf16 copies of the weights from the FP32 masters. */
+int bdg_mlp_refresh(const bdg_mlp_params *p, void *stream);
+/* Codes of n rows X * scale (device float [n][d]) through the network. */
+int bdg_mlp_encode(const bdg_mlp_params *p, const float *X, uint32_t n, float scale,
+                   uint64_t *out_codes, void *stream);
+/* C [M][N] (ldc) = A B^T for bf16 A [M][lda] and B [N][ldb] (K % 32 == 0,
+ * lda, ldb multiples of 8), FP32 accumulation: the product the network uses. */
+int bdg_gemm_nt_bf16(const uint16_t *A, uint32_t lda, const uint16_t *B, uint32_t ldb, uint32_t M,
+                     uint32_t N, uint32_t K, float *C, uint32_t ldc, void *stream);
+
 /* ------------------------------------------------------------- autotune --- */
 
 /*

@@ -69,6 +69,31 @@ class BatchInfo(ctypes.Structure):
 ORDER_LONGEST_FIRST, ORDER_SHARD = 0, 1
 
 
+class MlpParams(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_uint32), ("h", ctypes.c_uint32), ("bits", ctypes.c_uint32),
+                ("W1", ctypes.c_void_p), ("b1", ctypes.c_void_p),
+                ("W2", ctypes.c_void_p), ("b2", ctypes.c_void_p),
+                ("W1b", ctypes.c_void_p), ("W2b", ctypes.c_void_p), ("W2bt", ctypes.c_void_p)]
+
+
+class MlpActs(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_uint32), ("rows_pad", ctypes.c_uint32),
+                ("Xb", ctypes.c_void_p), ("Xt", ctypes.c_void_p), ("H1", ctypes.c_void_p),
+                ("H1b", ctypes.c_void_p), ("H1t", ctypes.c_void_p), ("Z2", ctypes.c_void_p),
+                ("H", ctypes.c_void_p), ("dZ2b", ctypes.c_void_p), ("dZ2t", ctypes.c_void_p),
+                ("dZ1t", ctypes.c_void_p)]
+
+
+class MlpGrads(ctypes.Structure):
+    _fields_ = [("W1", ctypes.c_void_p), ("b1", ctypes.c_void_p), ("W2", ctypes.c_void_p),
+                ("b2", ctypes.c_void_p)]
+
+
+class LossOpts(ctypes.Structure):
+    _fields_ = [("margin", ctypes.c_float), ("tau", ctypes.c_float), ("lam_q", ctypes.c_float),
+                ("lam_b", ctypes.c_float)]
+
+
 def make_opts(**kw) -> KnnOpts:
     o = KnnOpts()
     o.struct_size = ctypes.sizeof(KnnOpts)
@@ -97,6 +122,18 @@ _SIGS = {
     "bdg_build_knn_batched_ex": [_p, _p, _u32, _u32, _u32, _p, _p, _p, _p],
     "bdg_autotune_build": [_p, _u32, _u32, _u32, _p, _p, _p, _p, _p, _sz],
     "bdg_autotune_batched": [_p, _p, _p, _p, _p, _p, _sz],
+    "bdg_encode": [_p, _u32, _u32, _p, _u32, _p, _p],
+    "bdg_pack_signs": [_p, _u32, _u32, _p, _p],
+    "bdg_float_knn": [_p, _u32, _p, _u32, _u32, _u32, _p, _p, _p, _p],
+    "bdg_mlp_gather": [_p, _u32, _p, _u32, ctypes.c_float, _p, _p],
+    "bdg_mlp_forward": [_p, _p, _p],
+    "bdg_triplet_loss": [_p, _u32, _u32, _p, _p, _p, _p, _p],
+    "bdg_mlp_backward": [_p, _p, _p, _p],
+    "bdg_adam_step": [_p, _p, _p, _p, _sz, _u32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                      ctypes.c_float, _p],
+    "bdg_mlp_refresh": [_p, _p],
+    "bdg_mlp_encode": [_p, _p, _u32, ctypes.c_float, _p, _p],
+    "bdg_gemm_nt_bf16": [_p, _u32, _p, _u32, _u32, _u32, _u32, _p, _u32, _p],
     "bdg_status_string": [ctypes.c_int],
     "bdg_last_error": [],
     "bdg_version": [],
@@ -299,3 +336,132 @@ def autotune_build(codes, K: int, bits: int | None = None, row_block: int = 0, s
     _check(lib().bdg_autotune_build(_ptr(codes), n, bits, K, _ptr(out[0]), _ptr(out[1]),
                                     ctypes.byref(o), _stream(stream), rep, len(rep)))
     return o, rep.value.decode()
+
+
+# ---------------------------------------------------- binarisers, float kNN
+
+def encode_srp(x, proj, stream=None):
+    """Sign-of-random-projection codes of x (float32 [n][d]) with proj
+    (float32 [d][bits]), on the GPU: int64 [n][bits/64] (uint64 bit patterns)."""
+    import torch
+    n, d = x.shape
+    bits = proj.shape[1]
+    out = torch.empty((n, bits // 64), dtype=torch.int64, device=x.device)
+    _check(lib().bdg_encode(_ptr(x), n, d, _ptr(proj), bits, _ptr(out), _stream(stream)))
+    return out
+
+
+def pack_signs(z, stream=None):
+    import torch
+    n, bits = z.shape
+    out = torch.empty((n, bits // 64), dtype=torch.int64, device=z.device)
+    _check(lib().bdg_pack_signs(_ptr(z), n, bits, _ptr(out), _stream(stream)))
+    return out
+
+
+def float_knn(queries, base, K: int, exclude=None, stream=None):
+    """Exact squared-L2 kNN in FP32: (idx int32 [nq][K], dist float32 [nq][K])."""
+    import torch
+    nq, d = queries.shape
+    out = (torch.empty((nq, K), dtype=torch.int32, device=queries.device),
+           torch.empty((nq, K), dtype=torch.float32, device=queries.device))
+    _check(lib().bdg_float_knn(_ptr(queries), nq, _ptr(base), base.shape[0], d, K,
+                               _ptr(exclude), _ptr(out[0]), _ptr(out[1]), _stream(stream)))
+    return out
+
+
+def gemm_nt_bf16(A, B, stream=None):
+    """C = A B^T for bf16 bit patterns A [M][K], B [N][K] (int16 tensors): float32 [M][N]."""
+    import torch
+    M, K = A.shape
+    N = B.shape[0]
+    C = torch.empty((M, N), dtype=torch.float32, device=A.device)
+    _check(lib().bdg_gemm_nt_bf16(_ptr(A), K, _ptr(B), K, M, N, K, _ptr(C), N, _stream(stream)))
+    return C
+
+
+class Mlp:
+    """Device state of the learned encoder d -> h -> bits (tanh) and its
+    training step, all through the C ABI (bdg_mlp_*, bdg_triplet_loss,
+    bdg_adam_step). Weights: W1 [h][d], W2 [bits][h] (FP32 masters)."""
+
+    def __init__(self, W1, b1, W2, b2, device="cuda"):
+        import torch
+        f32 = dict(dtype=torch.float32, device=device)
+        self.W1 = torch.as_tensor(W1, **f32).contiguous()
+        self.b1 = torch.as_tensor(b1, **f32).contiguous()
+        self.W2 = torch.as_tensor(W2, **f32).contiguous()
+        self.b2 = torch.as_tensor(b2, **f32).contiguous()
+        self.h, self.d = self.W1.shape
+        self.bits = self.W2.shape[0]
+        i16 = dict(dtype=torch.int16, device=device)
+        self.W1b = torch.empty((self.h, self.d), **i16)
+        self.W2b = torch.empty((self.bits, self.h), **i16)
+        self.W2bt = torch.empty((self.h, self.bits), **i16)
+        self.params = MlpParams(self.d, self.h, self.bits, _vp(self.W1), _vp(self.b1),
+                                _vp(self.W2), _vp(self.b2), _vp(self.W1b), _vp(self.W2b),
+                                _vp(self.W2bt))
+        self.grads_t = [torch.zeros_like(t) for t in (self.W1, self.b1, self.W2, self.b2)]
+        self.grads = MlpGrads(*[_vp(t) for t in self.grads_t])
+        self.moments = [(torch.zeros_like(t), torch.zeros_like(t))
+                        for t in (self.W1, self.b1, self.W2, self.b2)]
+        self.step_count = 0
+        self.refresh()
+
+    def refresh(self, stream=None):
+        _check(lib().bdg_mlp_refresh(ctypes.byref(self.params), _stream(stream)))
+
+    def acts(self, rows_pad, train=True, device="cuda"):
+        import torch
+        assert rows_pad % 32 == 0
+        i16 = dict(dtype=torch.int16, device=device)
+        f32 = dict(dtype=torch.float32, device=device)
+        t = dict(Xb=torch.empty((rows_pad, self.d), **i16),
+                 Xt=torch.empty((self.d, rows_pad), **i16) if train else None,
+                 H1=torch.empty((rows_pad, self.h), **f32),
+                 H1b=torch.empty((rows_pad, self.h), **i16),
+                 H1t=torch.empty((self.h, rows_pad), **i16),
+                 Z2=torch.empty((rows_pad, self.bits), **f32),
+                 H=torch.empty((rows_pad, self.bits), **f32),
+                 dZ2b=torch.empty((rows_pad, self.bits), **i16) if train else None,
+                 dZ2t=torch.empty((self.bits, rows_pad), **i16) if train else None,
+                 dZ1t=torch.empty((self.h, rows_pad), **i16) if train else None,
+                 mu=torch.empty(self.bits, **f32), loss=torch.zeros(1, **f32))
+        a = MlpActs(0, rows_pad, *[_vp(t[k]) for k in ("Xb", "Xt", "H1", "H1b", "H1t", "Z2", "H",
+                                                       "dZ2b", "dZ2t", "dZ1t")])
+        return a, t
+
+    def gather(self, a, X, idx, rows, scale=1.0, stream=None):
+        _check(lib().bdg_mlp_gather(_ptr(X), self.d, _ptr(idx), rows, float(scale),
+                                    ctypes.byref(a), _stream(stream)))
+
+    def forward(self, a, stream=None):
+        _check(lib().bdg_mlp_forward(ctypes.byref(self.params), ctypes.byref(a), _stream(stream)))
+
+    def loss(self, a, t, T, margin=2.0, tau=4.0, lam_q=0.1, lam_b=0.01, stream=None):
+        o = LossOpts(margin, tau, lam_q, lam_b)
+        _check(lib().bdg_triplet_loss(ctypes.byref(a), self.bits, T, ctypes.byref(o),
+                                      _ptr(t["mu"]), _vp(self.grads_t[3]), _ptr(t["loss"]),
+                                      _stream(stream)))
+
+    def backward(self, a, stream=None):
+        _check(lib().bdg_mlp_backward(ctypes.byref(self.params), ctypes.byref(a),
+                                      ctypes.byref(self.grads), _stream(stream)))
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        self.step_count += 1
+        for p, g, (m, v) in zip((self.W1, self.b1, self.W2, self.b2), self.grads_t, self.moments):
+            _check(lib().bdg_adam_step(_ptr(p), _ptr(g), _ptr(m), _ptr(v), p.numel(),
+                                       self.step_count, lr, beta1, beta2, eps, _stream(stream)))
+        self.refresh(stream)
+
+    def encode(self, X, scale=1.0, stream=None):
+        import torch
+        out = torch.empty((X.shape[0], self.bits // 64), dtype=torch.int64, device=X.device)
+        _check(lib().bdg_mlp_encode(ctypes.byref(self.params), _ptr(X), X.shape[0], float(scale),
+                                    _ptr(out), _stream(stream)))
+        return out
+
+
+def _vp(t):
+    return None if t is None else t.data_ptr()

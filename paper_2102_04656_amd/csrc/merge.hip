@@ -14,67 +14,13 @@
 #include <stdint.h>
 
 #include "kernels.h"
+#include "wave_topk64.h"
 
 namespace bdg {
 
 namespace {
 
 constexpr int kW = 64;
-constexpr uint64_t kNone64 = ~0ull;
-
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int m) {
-  uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, m, kW);
-  uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), m, kW);
-  return ((uint64_t)hi << 32) | lo;
-}
-
-__device__ __forceinline__ uint64_t shfl_u64(uint64_t x, int src) {
-  uint32_t lo = (uint32_t)__shfl((int)(uint32_t)x, src, kW);
-  uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(x >> 32), src, kW);
-  return ((uint64_t)hi << 32) | lo;
-}
-
-__device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
-__device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b) { return a < b ? b : a; }
-
-__device__ __forceinline__ uint64_t sort64_u64(uint64_t x, uint32_t lane) {
-#pragma unroll
-  for (int k = 2; k <= kW; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      uint64_t y = shfl_xor_u64(x, j);
-      bool up = (lane & k) == 0;
-      bool lower = (lane & j) == 0;
-      x = (lower == up) ? umin64(x, y) : umax64(x, y);
-    }
-  }
-  return x;
-}
-
-template <int NR>
-__device__ __forceinline__ void merge_into(uint64_t (&R)[NR], uint64_t x_sorted, uint32_t lane) {
-  const uint64_t xr = shfl_u64(x_sorted, kW - 1 - lane);
-  R[NR - 1] = umin64(R[NR - 1], xr);
-#pragma unroll
-  for (int j = NR / 2; j >= 1; j >>= 1) {
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      if ((r & j) == 0) {
-        uint64_t a = R[r], b = R[r + j];
-        R[r] = umin64(a, b);
-        R[r + j] = umax64(a, b);
-      }
-    }
-  }
-#pragma unroll
-  for (int j = kW / 2; j >= 1; j >>= 1) {
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      uint64_t y = shfl_xor_u64(R[r], j);
-      R[r] = (lane & j) ? umax64(R[r], y) : umin64(R[r], y);
-    }
-  }
-}
 
 template <int NR>
 __global__ __launch_bounds__(256) void merge_lists_kernel(const uint32_t* __restrict__ in_idx,
@@ -120,15 +66,18 @@ __global__ __launch_bounds__(256) void merge_lists_kernel(const uint32_t* __rest
           }
           drop = lo < N && Rl[lo] == x;
         }
-        const uint64_t prev = shfl_u64(x, lane == 0 ? 0 : (int)lane - 1);
+        const uint64_t prev =
+            ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(x >> 32), lane == 0 ? 0 : (int)lane - 1,
+                                        kW) << 32) |
+            (uint32_t)__shfl((int)(uint32_t)x, lane == 0 ? 0 : (int)lane - 1, kW);
         if (lane > 0 && prev == x) drop = true;
         if (__any(drop)) {
           if (drop) x = kNone64;
-          x = sort64_u64(x, lane);
+          x = wave_sort64_u64(x, lane);
         }
         __builtin_amdgcn_wave_barrier();
       }
-      merge_into<NR>(R, x, lane);
+      merge64_into<NR>(R, x, lane);
     }
   }
   const size_t o = (size_t)row * K;

@@ -1,0 +1,180 @@
+"""GPU parity of the binarisers, the float-kNN ground truth and the learned
+encoder's training kernels, against the FP64 CPU oracle (oracle.learned).
+
+Floating point, so the bars are tolerances derived from the arithmetic:
+  * SRP codes: a GPU bit may differ from the FP64 bit only where the
+    projection is within 1e-5 of zero relative to |x| |w| (FP32 rounding of a
+    512-term dot product is ~1e-6 relative).
+  * BF16 products: |C - C64| <= 2^-8 * sum_k |a_k b_k| per element for bf16
+    operands rounded from FP32 (the inputs here are exact bf16, so FP32
+    accumulation error ~1e-6 relative is all that remains: bar 1e-5).
+  * Network forward/backward: relative L2 error per tensor <= 2e-2 against
+    FP64 on the unrounded inputs (bf16 operand rounding, FP32 accumulation).
+  * Float kNN: the FP64 distances of the GPU's neighbours equal the exact K
+    smallest distances to 1e-5 relative (order may differ only inside such
+    near-ties).
+"""
+import numpy as np
+import pytest
+
+from oracle import learned as L
+from paper_2102_04656_amd import bdg, datagen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    bdg.lib()
+
+
+def cu(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return (t if dtype is None else t.to(dtype)).cuda()
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def bf16_round(x):
+    """float32 -> nearest-even bf16, returned as float32 values and int16 patterns."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    pat = u.astype(np.uint16)
+    return (pat.astype(np.uint32) << 16).view(np.float32), pat.view(np.int16)
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+@pytest.mark.parametrize("n,d,bits", [(3000, 512, 256), (77, 16, 64), (130, 96, 1024)])
+def test_srp_encode_vs_fp64(n, d, bits):
+    x = datagen.gmm_features(n, d, n_comp=20, centre_std=2.0, seed=n)
+    w = datagen.gaussian_projection(d, bits, seed=bits)
+    got = host(bdg.encode_srp(cu(x), cu(w))).view(np.uint64)
+    want = L.srp_encode(x, w)
+    diff = datagen.unpack_bits(got) != datagen.unpack_bits(want)
+    margin = L.srp_margin(x, w)
+    assert (margin[diff] <= 1e-5).all(), f"{diff.sum()} bits differ, max margin {margin[diff].max()}"
+    assert diff.sum() <= max(1, n * bits // 100000)
+
+
+def test_pack_signs():
+    g = np.random.default_rng(1)
+    z = g.standard_normal((333, 128)).astype(np.float32)
+    z[0, :] = 0.0  # strict sign: zero is a 0 bit
+    got = host(bdg.pack_signs(cu(z))).view(np.uint64)
+    assert np.array_equal(got, datagen.pack_bits((z > 0).astype(np.uint8)))
+
+
+def test_gemm_nt_bf16_vs_fp64():
+    g = np.random.default_rng(2)
+    M, N, K = 100, 70, 96  # ragged tiles in M and N
+    a, ab = bf16_round(g.standard_normal((M, K)).astype(np.float32))
+    b, bb = bf16_round(g.standard_normal((N, K)).astype(np.float32))
+    C = host(bdg.gemm_nt_bf16(cu(ab), cu(bb)))
+    want = a.astype(np.float64) @ b.astype(np.float64).T
+    scale = np.abs(a).astype(np.float64) @ np.abs(b).astype(np.float64).T
+    assert (np.abs(C - want) <= 1e-5 * scale + 1e-30).all()
+
+
+def make_batch(seed, d, h, bits, T):
+    g = np.random.default_rng(seed)
+    W1 = (g.standard_normal((h, d)) / np.sqrt(d)).astype(np.float32)
+    b1 = (0.1 * g.standard_normal(h)).astype(np.float32)
+    W2 = (g.standard_normal((bits, h)) / np.sqrt(h)).astype(np.float32)
+    b2 = (0.1 * g.standard_normal(bits)).astype(np.float32)
+    X = g.standard_normal((3 * T + 5, d)).astype(np.float32)
+    idx = g.permutation(3 * T + 5)[:3 * T].astype(np.uint32)
+    return W1, b1, W2, b2, X, idx
+
+
+@pytest.mark.parametrize("d,h,bits,T", [(64, 128, 64, 20), (512, 1024, 256, 100)])
+def test_mlp_training_step_vs_fp64(d, h, bits, T):
+    W1, b1, W2, b2, X, idx = make_batch(d + T, d, h, bits, T)
+    net = bdg.Mlp(W1, b1, W2, b2)
+    rows_pad = (3 * T + 31) // 32 * 32
+    a, t = net.acts(rows_pad)
+    net.gather(a, cu(X), cu(idx), 3 * T)
+    net.forward(a)
+    net.loss(a, t, T)
+    net.backward(a)
+    cache = L.mlp_forward(X[idx], W1.T, b1, W2.T, b2)
+    loss, dH = L.triplet_loss(cache["H"], bits)
+    grads = L.mlp_backward(cache, dH, W2.T)
+    Hg = host(t["H"])[:3 * T]
+    assert rel_l2(Hg, cache["H"]) < 2e-2
+    assert abs(float(host(t["loss"])[0]) - loss) < 2e-2 * abs(loss)
+    assert rel_l2(host(net.grads_t[0]), grads["W1"].T) < 2e-2
+    assert rel_l2(host(net.grads_t[1]), grads["b1"]) < 2e-2
+    assert rel_l2(host(net.grads_t[2]), grads["W2"].T) < 2e-2
+    assert rel_l2(host(net.grads_t[3]), grads["b2"]) < 2e-2
+    # the code of a row is the sign of its pre-activation
+    z2 = host(t["Z2"])[:3 * T]
+    codes = host(net.encode(cu(X[idx]))).view(np.uint64)
+    assert np.array_equal(codes, datagen.pack_bits((z2 > 0).astype(np.uint8)))
+
+
+def test_adam_vs_fp64():
+    import torch
+    g = np.random.default_rng(3)
+    p0 = g.standard_normal(1000).astype(np.float32)
+    p = cu(p0.copy())
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    pr, mr, vr = p0.astype(np.float64), np.zeros(1000), np.zeros(1000)
+    for step in range(1, 6):
+        gr = g.standard_normal(1000).astype(np.float32)
+        assert bdg.lib().bdg_adam_step(bdg._ptr(p), bdg._ptr(cu(gr)), bdg._ptr(m), bdg._ptr(v),
+                                       1000, step, 1e-2, 0.9, 0.999, 1e-8, None) == 0
+        pr, mr, vr = L.adam_step(pr, gr.astype(np.float64), mr, vr, step, lr=1e-2)
+    assert np.allclose(host(p), pr, rtol=1e-5, atol=1e-6)
+
+
+def check_float_knn(q, base, K, gi, gd, rows, exclude=None):
+    """GPU rows are exact kNN up to FP32 near-ties."""
+    same = 0
+    for r in rows:
+        ex = None if exclude is None else np.array([exclude[r]])
+        wi, wd = L.float_knn(q[r:r + 1], base, K, exclude=ex)
+        d_gpu = ((base[gi[r]].astype(np.float64) - q[r].astype(np.float64)) ** 2).sum(axis=1)
+        assert np.allclose(np.sort(d_gpu), wd[0], rtol=1e-5, atol=1e-6), f"row {r}"
+        assert np.allclose(gd[r], wd[0], rtol=1e-4, atol=1e-4)
+        assert len(set(gi[r].tolist())) == K and (exclude is None or exclude[r] not in gi[r])
+        same += np.array_equal(gi[r], wi[0])
+    return same
+
+
+def test_float_knn_small_full():
+    x = datagen.gmm_features(2000, 64, n_comp=40, centre_std=2.0, seed=9)
+    gi, gd = (host(t) for t in bdg.float_knn(cu(x), cu(x), 10,
+                                             exclude=cu(np.arange(2000, dtype=np.int32))))
+    gi = gi.view(np.uint32)
+    same = check_float_knn(x, x, 10, gi, gd, range(2000), exclude=np.arange(2000))
+    assert same >= 1990
+
+
+def test_float_knn_blocks_and_padding():
+    # more queries than one query chunk (8192) and more base rows than one
+    # column block (65536): the running lists cross blocks
+    x = datagen.gmm_features(70_000, 32, n_comp=300, centre_std=2.0, seed=10)
+    q = x[:9000]
+    gi, gd = (host(t) for t in bdg.float_knn(cu(q), cu(x), 33,
+                                             exclude=cu(np.arange(9000, dtype=np.int32))))
+    gi = gi.view(np.uint32)
+    rows = np.unique(np.r_[0, 8191, 8192, 8999, np.random.default_rng(1).integers(0, 9000, 40)])
+    check_float_knn(q, x, 33, gi, gd, rows, exclude=np.arange(9000))
+    # K larger than the base: padding
+    gi, gd = (host(t) for t in bdg.float_knn(cu(x[:5]), cu(x[:3]), 6))
+    gi = gi.view(np.uint32)
+    assert (gi[:, 3:] == 0xFFFFFFFF).all() and np.isinf(gd[:, 3:]).all()
