@@ -156,6 +156,31 @@ def cpu_baseline(codes, K, gpu_out, target_s):
                 parity_on_sample=parity)
 
 
+def recall_leg():
+    """Learned vs sign-of-random-projection codes at equal length on the 1M x 512
+    Gaussian mixture: recall@64 (Eq. 3) of the exact Hamming graph of each
+    code set against exact float kNN over 10k sampled rows. Not timed as
+    part of the build; the encode and graph times are reported beside it."""
+    from paper_2102_04656_amd import datagen, learned_codes
+    w = datagen.WORKLOADS["gmm-1m-512d"]
+    log("[bench] recall leg: training the encoder on gmm-1m-512d")
+    res, _ = learned_codes.experiment(
+        n=w["n"], d=w["d"], n_comp=w["n_comp"], centre_std=w["centre_std"], seed=w["seed"],
+        proj_seed=w["proj_seed"], bits=w["code_bits"], K_train=w["K_train"],
+        K_eval=w["K_eval"], train_rows=w["train_rows"], eval_queries=w["eval_queries"])
+    K = w["K_eval"]
+    return {"workload": "gmm-1m-512d", "K": K, "bits": w["code_bits"],
+            "learned": res["recall_learned"], "srp": res["recall_srp"],
+            "gain": res["recall_learned"] - res["recall_srp"],
+            "train_steps": res["steps"], "train_seconds": res["train_seconds"],
+            "encode_ms_learned": res["encode_seconds_learned"] * 1e3,
+            "encode_ms_srp": res["encode_seconds_srp"] * 1e3,
+            "graph_ms_learned": res["graph_seconds_learned"] * 1e3,
+            "graph_ms_srp": res["graph_seconds_srp"] * 1e3,
+            "float_knn_ms": {"train_pairs": res["train_knn_seconds"] * 1e3,
+                             "eval_truth": res["exact_knn_seconds"] * 1e3}}
+
+
 def bench_batched(args, w):
     """Many shards in one persistent launch, replayed as a HIP graph (schedule
     autotuned once, outside the timed region)."""
@@ -251,6 +276,9 @@ def main():
                     help="also time the other distance path (reported, not the value)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--recall", action=argparse.BooleanOptionalAction, default=True,
+                    help="after the timed builds, train the learned encoder on the 1M x 512 "
+                         "mixture and report recall@64 of learned vs SRP codes (~30 s)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -339,6 +367,9 @@ def main():
         result["cpu_baseline"] = cpu_baseline(codes, K, outs, args.cpu_seconds)
         log(f"[bench] cpu baseline: {result['cpu_baseline']['value']:.3e} pair-dist/s on "
             f"{result['cpu_baseline']['cores']} threads")
+    if args.recall:
+        del outs, codes_dev
+        result["recall"] = recall_leg()
     print(json.dumps(result), flush=True)
 
 
