@@ -43,6 +43,55 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# Sources that define each timed kernel: a recorded HBM-traffic figure is
+# reported only while they are unchanged since the counters were taken.
+KERNEL_SOURCES = {
+    "knn_mfma_run_kernel": ["tile_mfma_kern.h", "wave_topk.h", "tile_mfma.hip", "kernels.h"],
+    "knn_mfma_batched_kernel": ["tile_mfma_kern.h", "wave_topk.h", "tile_mfma.hip", "kernels.h"],
+    "knn_popc_kernel": ["knn_tiles.hip", "wave_topk.h", "kernels.h"],
+}
+CALIB_BYTES = 256 << 20
+
+
+def kernel_source_hash(kernel: str) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2102_04656_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary
+    of this kernel and workload (scaled by the copy-kernel calibration), or
+    None if there is none or the kernel's sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"traffic__{kernel}__{workload}.md")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("traffic-record: "):
+                rec = json.loads(line[len("traffic-record: "):])
+    if not rec or rec.get("source_sha256_16") != kernel_source_hash(kernel):
+        return None
+    return rec
+
+
+def copy_calibration():
+    """A plain streaming kernel of known size for counter calibration:
+    CALIB_BYTES read and CALIB_BYTES written (run outside the timed region)."""
+    import torch
+    src = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 class HipEvents:
     """hipEvent_t handles created through the HIP runtime's C API."""
 
@@ -238,6 +287,14 @@ def bench_batched(args, w):
                      "kernel": "knn_mfma_batched_kernel", "kernel_avg_ms": launch_ms,
                      "ops_per_pair": 2 * bits, "pairs_per_launch": pairs},
     }
+    rec = recorded_traffic("knn_mfma_batched_kernel", args.workload)
+    if rec is not None:
+        result["roofline"]["traffic"] = rec["bytes_per_launch"]
+        result["roofline"]["traffic_source"] = (
+            f"profiles/traffic__knn_mfma_batched_kernel__{args.workload}.md (FETCH_SIZE + "
+            f"WRITE_SIZE per launch, copy-calibrated)")
+    if args.copy_calibration:
+        copy_calibration()
     if not args.no_cpu_baseline:
         import oracle
         g = np.random.default_rng(2021)
@@ -276,6 +333,9 @@ def main():
                     help="also time the other distance path (reported, not the value)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed builds, run a streaming kernel of known size "
+                         "(for scaling hardware byte counters)")
     ap.add_argument("--recall", action=argparse.BooleanOptionalAction, default=True,
                     help="after the timed builds, train the learned encoder on the 1M x 512 "
                          "mixture and report recall@64 of learned vs SRP codes (~30 s)")
@@ -327,6 +387,7 @@ def main():
     else:
         ops_pair, peak, bound = 2 * bits // 32, PEAK_VALU_TOPS, "alu"
     achieved = kern["pairs_per_launch"] * ops_pair / (kern["avg_ms"] * 1e-3) / 1e12
+    kname = "knn_mfma_run_kernel" if main_path == "mfma" else "knn_popc_kernel"
     result = {
         "metric": METRIC,
         "value": pairs / (ms * 1e-3),
@@ -345,11 +406,19 @@ def main():
                    "centres": w["n_centres"], "flip_p": w["p"], "seed": w["seed"]},
         "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TOP/s",
                      "frac": achieved / peak, "traffic": None,
-                     "kernel": "knn_mfma_run_kernel" if main_path == "mfma" else "knn_popc_kernel",
+                     "kernel": kname,
                      "kernel_avg_ms": kern["avg_ms"],
                      "ops_per_pair": ops_pair,
                      "pairs_per_launch": kern["pairs_per_launch"]},
     }
+    rec = recorded_traffic(kname, args.workload)
+    if rec is not None:
+        result["roofline"]["traffic"] = rec["bytes_per_launch"]
+        result["roofline"]["traffic_source"] = (
+            f"profiles/traffic__{kname}__{args.workload}.md (FETCH_SIZE + WRITE_SIZE per launch, "
+            f"copy-calibrated)")
+    if args.copy_calibration:
+        copy_calibration()
     for name, r in runs.items():
         if name == main_path:
             continue
