@@ -16,10 +16,13 @@
 // contiguous 16-byte access per lane, into LDS or into registers. The product
 // pairs the same code bit of both operands (A and B share the lane-to-k map).
 //
-// Work split. A work-group is 4 waves; each wave owns 16 QG queries (rows)
-// held as B operands in registers for the whole launch. The 4 waves share a
-// stream of candidate stages (CT codes each) copied from HBM straight into LDS
-// (double-buffered, one copy per work-group) and read back as A operands.
+// Work split. A work-group has 4 compute waves; each owns 16 QG queries (rows)
+// held as B operands in registers for the whole launch. They share a stream of
+// candidate stages (CT codes each) copied from HBM straight into a ring of LDS
+// slots (one copy per work-group) and read back as A operands. Where registers
+// allow two waves on a SIMD (codes up to 320 bits with K <= 64, up to 512 bits
+// with larger K) a fifth wave only streams the stages and publishes a count of
+// landed ones; otherwise the compute waves claim and copy stages themselves.
 //
 // Filter. The accumulator starts at the per-query bias 2 thr - b, so after
 // the contraction acc = 2 (thr - ham): a candidate can enter the list only if

@@ -151,16 +151,62 @@ template <int SV4, int NST>
 struct TileRing {
   v4i stage[NST][SV4];
   uint32_t landed[NST], freed[NST], claimed;
+  uint32_t published;  // with a producer: stages below this count have landed
 };
+
+// The copy wave of a work-group with a producer (codes up to 512 bits): it
+// streams the nst stages of the job into the ring and publishes them in order
+// (published = number of stages whose copies are complete), keeping up to D
+// stages in flight; a slot is refilled only after all kWaves compute waves
+// counted themselves done with its previous stage (freed[slot]). Before it
+// sleeps on a slot it publishes everything it has issued, so that the compute
+// waves never wait on a finished copy.
+template <int SV4, int NST, int D>
+__device__ __forceinline__ void produce_stages(TileRing<SV4, NST>& ring, const v4i* __restrict__ src0,
+                                               uint32_t nst, uint32_t lane) {
+  constexpr int LPS = SV4 / 64;  // copies per lane per stage
+  static_assert(D >= 1 && D * LPS <= 63, "stages in flight exceed the vector-memory counter");
+  uint32_t pub = 0;  // stages below pub are published
+  auto publish_upto = [&](uint32_t end) {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    if (end > pub && lane == 0)
+      __hip_atomic_store(&ring.published, end, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    pub = end > pub ? end : pub;
+  };
+#pragma unroll 1
+  for (uint32_t t = 0; t < nst; ++t) {
+    const uint32_t slot = t % NST;
+    if (t >= (uint32_t)NST) {
+      const uint32_t need = kWaves * (t / NST);
+      if (__hip_atomic_load(&ring.freed[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <
+          need) {
+        BDG_WAIT_VMCNT(0);
+        publish_upto(t);
+        while (__hip_atomic_load(&ring.freed[slot], __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP) < need)
+          __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    load_stage_wave<SV4>(src0 + (size_t)t * SV4, ring.stage[slot], lane);
+    if (t + 1 - pub > (uint32_t)D) {  // the oldest stage in flight must land first
+      BDG_WAIT_VMCNT(D * LPS);
+      publish_upto(t + 1 - D);
+    }
+  }
+  BDG_WAIT_VMCNT(0);
+  publish_upto(nst);
+}
 
 // The work of one work-group on one tile job; q0_wg = first job row of the
 // work-group (the job's rows are split over work-groups of 4 QW rows).
-template <int W, int NR, int QG, int GPS, int NST>
+template <int W, int NR, int QG, int GPS, int NST, bool PROD>
 __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
                                           const uint64_t* __restrict__ codes, uint32_t K,
                                           uint32_t bits, uint32_t IB, const TileJob& job,
                                           uint32_t q0_wg, TileRing<GPS * W * 64, NST>& ring,
                                           uint32_t* state) {
+  static_assert(!PROD || GPS % 2 == 0, "the producer loop keeps accumulator parity across stages");
   constexpr int QW = 16 * QG;        // queries per wave
   constexpr int CT = 16 * GPS;       // codes per stage
   constexpr int SV4 = GPS * W * 64;  // 16-byte chunks per stage
@@ -192,22 +238,34 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
   const uint32_t cstart = cb & ~15u;
   const uint32_t nst = (ce - cstart + CT - 1) / CT;
   const v4i* src0 = frags + (size_t)(cstart / 16) * W * 64;
-  // Stage ring control. The waves move through the stages independently (a
-  // wave that merges lists does not hold the others back), within the slack
-  // the ring allows: landed[b] = 1 + generation of the last stage whose copy
-  // into slot b completed; freed[b] counts the (wave, stage) pairs done
-  // reading slot b; claimed = next stage to be copied. The first wave to
-  // reach a stage start claims the copy of the stage NST - 1 ahead, issues it
-  // (the whole stage) once every wave has finished the slot's previous stage,
-  // and publishes it at its next stage start.
+  // Stage ring control. The compute waves move through the stages
+  // independently (a wave that merges lists does not hold the others back),
+  // within the slack the ring allows: landed[b] = 1 + generation of the last
+  // stage whose copy into slot b completed; freed[b] counts the (wave, stage)
+  // pairs done reading slot b. With a producer wave, that wave does every
+  // copy (produce_stages). Without one, claimed = next stage to be copied: the
+  // first compute wave to reach a stage start claims the copy of the stage
+  // NST - 1 ahead, issues it (the whole stage) once every wave has finished
+  // the slot's previous stage, and publishes it at its next stage start.
   if (tid < NST) {
-    ring_landed[tid] = tid < NST - 1 ? 1u : 0u;  // stages 0..NST-2: the prologue copies
+    ring_landed[tid] = (!PROD && tid < NST - 1) ? 1u : 0u;  // prologue copies
     ring_freed[tid] = 0;
   }
-  if (tid == 0) ring_claimed = NST - 1;
+  if (tid == 0) ring.published = 0;
+  if constexpr (PROD) {
+    if (wave == kWaves) {
+      lds_barrier();  // the ring words are initialised (pairs with the compute waves' barrier)
+      constexpr int LPS = SV4 / 64;
+      constexpr int DM = 63 / LPS;
+      produce_stages<SV4, NST, (NST - 1 < DM ? NST - 1 : DM)>(ring, src0, nst, lane);
+      return;
+    }
+  } else {
+    if (tid == 0) ring_claimed = NST - 1;
 #pragma unroll
-  for (int p = 0; p < NST - 1; ++p)
-    if ((uint32_t)p < nst) load_stage<SV4>(src0 + (size_t)p * SV4, stage[p], tid);
+    for (int p = 0; p < NST - 1; ++p)
+      if ((uint32_t)p < nst) load_stage<SV4>(src0 + (size_t)p * SV4, stage[p], tid);
+  }
 
   // Running lists of the wave's rows (the output rows hold the merge of the
   // earlier column blocks unless this is the first).
@@ -243,8 +301,12 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
     csub[gq] = 0;
   }
 
-  BDG_WAIT_VMCNT(0);  // prologue stage copies (all threads) and ring init
-  __syncthreads();
+  if constexpr (PROD) {
+    __syncthreads();  // ring init (pairs with the producer's barrier)
+  } else {
+    BDG_WAIT_VMCNT(0);  // prologue stage copies (all threads) and ring init
+    __syncthreads();
+  }
 
   // Flush every query of group gq whose lanes are flagged in m (a ballot).
   auto flush_group = [&](const int gq, uint64_t m) {
@@ -313,44 +375,53 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
     }
   };
 
-  auto issue = [&](v4i (&acc)[QG], int (&bb)[QG], const v4i (&a)[W]) {
+  // The contraction of one 16-code group: W layers (one per 64-bit word) of
+  // QG independent products. A scheduling fence after each layer keeps a
+  // chain's consecutive products QG issues apart (never back to back), and
+  // `work(s)` places a share of the vector work inside layer s.
+  auto issue_with = [&](v4i (&acc)[QG], int (&bb)[QG], const v4i (&a)[W], auto&& work) {
 #pragma unroll
-    for (int s = 0; s < W; ++s)
+    for (int s = 0; s < W; ++s) {
 #pragma unroll
       for (int gq = 0; gq < QG; ++gq)
         acc[gq] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[s], bq[gq][s],
                                                         s == 0 ? biasC[gq] : acc[gq], 0, 0, 0);
+      work(s);
+      __builtin_amdgcn_sched_barrier(0);
+    }
 #pragma unroll
     for (int gq = 0; gq < QG; ++gq) bb[gq] = biasC[gq][0] + (int)bits;
+  };
+  auto issue = [&](v4i (&acc)[QG], int (&bb)[QG], const v4i (&a)[W]) {
+    issue_with(acc, bb, a, [](int) {});
   };
 
   // Per stage: the contraction of group g is issued before the filter of
   // group g - 1 (ping-pong accumulators), so the matrix cores keep busy while
   // the vector ALUs test. A group contracted before a merge tightened a
   // threshold just admits a superset; its keys use the bias it was contracted
-  // with. The operand reads of group g + 1 are pinned ahead of group g's
-  // contraction, and the test of group g - 1 is interleaved with it.
-  constexpr int kTestOps = 2 * QG;  // vector ops of the max-reduction, about
+  // with. The max-reduction of group g - 1 is spread over the layers of
+  // group g's contraction (query group gq in layer gq % W).
   auto issue_and_test = [&](v4i (&accN)[QG], int (&bbN)[QG], const v4i (&a)[W],
                             const v4i (&accP)[QG]) {
-    issue(accN, bbN, a);
-    const int mx = maxacc(accP);
+    int mx = accP[0][0];
+    issue_with(accN, bbN, a, [&](int s) {
 #pragma unroll
-    for (int i = 0; i < kTestOps && i < W * QG; ++i) {
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
-      __builtin_amdgcn_sched_group_barrier(0x002, 1, 0);  // one vector op
-    }
-    __builtin_amdgcn_sched_group_barrier(0x008, W * QG, 0);
+      for (int gq = 0; gq < QG; ++gq)
+        if (gq % W == s)
+          mx = max(mx, max(max(accP[gq][0], accP[gq][1]), max(accP[gq][2], accP[gq][3])));
+    });
     return mx;
   };
 
   v4i acc[2][QG];
   int bb[2][QG];
   uint32_t pend = 0xFFFFFFFFu;  // stage this wave copies and has not published
+  uint32_t avail = 0;           // with a producer: stages known to have landed
 #pragma unroll 1
   for (uint32_t st = 0; st < nst; ++st) {
     const uint32_t slot = st % NST;
-    if (pend != 0xFFFFFFFFu) {  // publish the copy issued one stage ago
+    if (!PROD && pend != 0xFFFFFFFFu) {  // publish the copy issued one stage ago
       BDG_WAIT_VMCNT(0);
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
       if (lane == 0)
@@ -358,13 +429,23 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
                            __HIP_MEMORY_SCOPE_WORKGROUP);
       pend = 0xFFFFFFFFu;
     }
-    while (__hip_atomic_load(&ring_landed[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <
-           st / NST + 1)
-      __builtin_amdgcn_s_sleep(1);
+    if constexpr (PROD) {
+      // The producer runs ahead: the count of landed stages is re-read only
+      // when this wave has caught up with the last value it saw.
+      while (st >= avail) {
+        avail = __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+            &ring.published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+        if (st >= avail) __builtin_amdgcn_s_sleep(1);
+      }
+    } else {
+      while (__hip_atomic_load(&ring_landed[slot], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP) < st / NST + 1)
+        __builtin_amdgcn_s_sleep(1);
+    }
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     const uint32_t t = st + NST - 1;
-    if (t < nst && __hip_atomic_load(&ring_claimed, __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_WORKGROUP) == t) {
+    if (!PROD && t < nst && __hip_atomic_load(&ring_claimed, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_WORKGROUP) == t) {
       uint32_t won = 0;
       if (lane == 0) {
         uint32_t expect = t;
@@ -439,16 +520,43 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
   }
 }
 
+// Launch shape per (code words W, list class NR: K <= 64 NR). Where the
+// compute waves' registers leave room for two waves on one SIMD (at most 256
+// each: codes up to 320 bits with 64 queries per wave, up to 512 bits with
+// fewer), a fifth wave is the stage producer; otherwise the compute waves
+// copy the stages themselves.
+constexpr bool use_producer(int W, int NR) { return NR == 1 ? W <= 5 : W <= 8; }
+constexpr int threads_of(int W, int NR) { return (kWaves + (use_producer(W, NR) ? 1 : 0)) * 64; }
+// 16-code groups per stage (even with a producer, so the ping-pong of
+// accumulators runs across stage boundaries).
+constexpr int stage_groups(int W, int NR) {
+  return use_producer(W, NR) ? (W <= 2 ? 4 : 2) : (W <= 5 ? 4 : (W <= 8 ? 2 : 1));
+}
+// Queries per wave / 16.
+constexpr int qgroups_of_nr(int NR) { return NR == 1 ? 4 : (NR == 2 ? 3 : 1); }
+constexpr size_t state_bytes(int K, int qg) {
+  return (size_t)kWaves * ((size_t)16 * qg * K + (size_t)16 * qg * kBuf + 64) * 4;
+}
+// Stage slots: with a producer as many as the LDS left by the largest lists of
+// the class holds (at most 8); without, the previous fixed depths.
+constexpr int stages_of(int W, int NR) {
+  if (!use_producer(W, NR)) return NR == 2 ? 2 : 3;
+  const size_t avail = 160 * 1024 - state_bytes(64 * NR, qgroups_of_nr(NR)) - 256;
+  const size_t n = avail / ((size_t)stage_groups(W, NR) * W * 1024);
+  return n > 8 ? 8 : (int)n;
+}
+
 // One (row block, column block) tile per launch; work-group g takes rows
 // [256 g, 256 g + 256) of the row block (4 QW = 256 rows at QG = 4).
 template <int W, int NR, int QG, int GPS, int NST>
-__global__ __launch_bounds__(256, 1) void knn_mfma_run_kernel(
+__global__ __launch_bounds__(threads_of(W, NR), 1) void knn_mfma_run_kernel(
     const v4i* __restrict__ frags, const uint64_t* __restrict__ codes, uint32_t K, uint32_t bits,
     uint32_t IB, TileJob job) {
   __shared__ TileRing<GPS * W * 64, NST> ring;
   extern __shared__ uint32_t state[];
-  tile_body<W, NR, QG, GPS, NST>(frags, codes, K, bits, IB, job, blockIdx.x * (kWaves * 16 * QG),
-                                 ring, state);
+  tile_body<W, NR, QG, GPS, NST, use_producer(W, NR)>(frags, codes, K, bits, IB, job,
+                                                      blockIdx.x * (kWaves * 16 * QG), ring,
+                                                      state);
 }
 
 // Many independent partitions in one persistent launch: every work-group
@@ -456,7 +564,7 @@ __global__ __launch_bounds__(256, 1) void knn_mfma_run_kernel(
 // from a shared counter until the list is exhausted. Items are ordered
 // longest first, so the uneven shards balance over the CUs.
 template <int W, int NR, int QG, int GPS, int NST>
-__global__ __launch_bounds__(256, 1) void knn_mfma_batched_kernel(
+__global__ __launch_bounds__(threads_of(W, NR), 1) void knn_mfma_batched_kernel(
     const v4i* __restrict__ frags, const uint64_t* __restrict__ codes, uint32_t K, uint32_t bits,
     uint32_t IB, const BatchItem* __restrict__ items, uint32_t nitems, uint32_t* counter,
     uint32_t* __restrict__ out_idx, uint16_t* __restrict__ out_dist) {
@@ -479,7 +587,8 @@ __global__ __launch_bounds__(256, 1) void knn_mfma_batched_kernel(
     job.fresh = 1;
     job.out_idx = out_idx + (size_t)b.row0 * K;
     job.out_dist = out_dist + (size_t)b.row0 * K;
-    tile_body<W, NR, QG, GPS, NST>(frags, codes, K, bits, IB, job, 0, ring, state);
+    tile_body<W, NR, QG, GPS, NST, use_producer(W, NR)>(frags, codes, K, bits, IB, job, 0, ring,
+                                                        state);
   }
 }
 
@@ -487,43 +596,23 @@ namespace {
 __global__ void zero_counter_kernel(uint32_t* counter) { *counter = 0; }
 }  // namespace
 
-// Launch shape per (W, list size). 16-code groups per stage: up to 4 (the
-// operands per stage, with the per-thread load count kept whole.
-template <int W>
-constexpr int stage_groups() {
-  return W <= 5 ? 4 : (W <= 8 ? 2 : 1);
-}
-// Queries per wave / 16 and stage buffers, so that lists, buffers and stages
-// fit the 160 KB of LDS of a CU (one work-group per CU).
-template <int NR>
-constexpr int run_qgroups() {
-  return NR == 1 ? 4 : (NR == 2 ? 3 : 1);
-}
-template <int NR>
-constexpr int run_stages() {
-  return NR == 2 ? 2 : 3;
-}
-
 inline int nr_of(uint32_t K) { return K <= 64 ? 1 : (K <= 128 ? 2 : 4); }
-inline int qg_of(uint32_t K) { return nr_of(K) == 1 ? 4 : (nr_of(K) == 2 ? 3 : 1); }
-inline int nst_of(uint32_t K) { return nr_of(K) == 2 ? 2 : 3; }
+inline int qg_of(uint32_t K) { return qgroups_of_nr(nr_of(K)); }
 
-inline uint32_t groups_of(uint32_t W) { return W <= 5 ? 4u : (W <= 8 ? 2u : 1u); }
-
-inline size_t run_state_bytes(uint32_t K, int qg) {
-  const size_t qw = 16u * qg;
-  return (size_t)kWaves * (qw * K + qw * kBuf + 64) * 4;
-}
+inline size_t run_state_bytes(uint32_t K, int qg) { return state_bytes((int)K, qg); }
 
 inline size_t run_lds_bytes(uint32_t W, uint32_t K) {
-  const size_t stage = (size_t)groups_of(W) * W * 1024;
-  return nst_of(K) * stage + run_state_bytes(K, qg_of(K));
+  const size_t stage = (size_t)stage_groups((int)W, nr_of(K)) * W * 1024;
+  return stages_of((int)W, nr_of(K)) * stage + run_state_bytes(K, qg_of(K));
 }
 
 template <int W, int NR>
 inline hipError_t launch_run_w(const RunArgs& a, hipStream_t stream) {
-  constexpr int QG = run_qgroups<NR>();
-  auto kern = knn_mfma_run_kernel<W, NR, QG, stage_groups<W>(), run_stages<NR>()>;
+  constexpr int QG = qgroups_of_nr(NR);
+  constexpr int GPS = stage_groups(W, NR);
+  constexpr int NST = stages_of(W, NR);
+  static_assert(NST >= 2, "stage ring needs two slots");
+  auto kern = knn_mfma_run_kernel<W, NR, QG, GPS, NST>;
   const size_t lds = run_state_bytes(a.K, QG);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -539,21 +628,24 @@ inline hipError_t launch_run_w(const RunArgs& a, hipStream_t stream) {
   job.fresh = a.fresh;
   job.out_idx = a.out_idx;
   job.out_dist = a.out_dist;
-  hipLaunchKernelGGL(kern, grid, dim3(256), lds, stream,
+  hipLaunchKernelGGL(kern, grid, dim3(threads_of(W, NR)), lds, stream,
                      reinterpret_cast<const v4i*>(a.frags), a.codes, a.K, a.bits, a.idx_bits, job);
   return hipGetLastError();
 }
 
 template <int W, int NR>
 inline hipError_t launch_batched_w(const BatchArgs& a, hipStream_t stream) {
-  constexpr int QG = run_qgroups<NR>();
-  auto kern = knn_mfma_batched_kernel<W, NR, QG, stage_groups<W>(), run_stages<NR>()>;
+  constexpr int QG = qgroups_of_nr(NR);
+  constexpr int GPS = stage_groups(W, NR);
+  constexpr int NST = stages_of(W, NR);
+  static_assert(NST >= 2, "stage ring needs two slots");
+  auto kern = knn_mfma_batched_kernel<W, NR, QG, GPS, NST>;
   const size_t lds = run_state_bytes(a.K, QG);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, stream, a.counter);
-  hipLaunchKernelGGL(kern, dim3(a.grid), dim3(256), lds, stream,
+  hipLaunchKernelGGL(kern, dim3(a.grid), dim3(threads_of(W, NR)), lds, stream,
                      reinterpret_cast<const v4i*>(a.frags), a.codes, a.K, a.bits, a.idx_bits,
                      a.items, a.nitems, a.counter, a.out_idx, a.out_dist);
   return hipGetLastError();
