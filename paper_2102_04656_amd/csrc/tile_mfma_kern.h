@@ -530,7 +530,7 @@ constexpr int threads_of(int W, int NR) { return (kWaves + (use_producer(W, NR) 
 // 16-code groups per stage (even with a producer, so the ping-pong of
 // accumulators runs across stage boundaries).
 constexpr int stage_groups(int W, int NR) {
-  return use_producer(W, NR) ? (W <= 2 ? 4 : 2) : (W <= 5 ? 4 : (W <= 8 ? 2 : 1));
+  return use_producer(W, NR) ? (W <= 4 ? 4 : 2) : (W <= 5 ? 4 : (W <= 8 ? 2 : 1));
 }
 // Queries per wave / 16.
 constexpr int qgroups_of_nr(int NR) { return NR == 1 ? 4 : (NR == 2 ? 3 : 1); }
