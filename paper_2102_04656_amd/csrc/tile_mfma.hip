@@ -16,13 +16,18 @@
 // contiguous 16-byte access per lane, into LDS or into registers. The product
 // pairs the same code bit of both operands (A and B share the lane-to-k map).
 //
-// Work split. A work-group has 4 compute waves; each owns 16 QG queries (rows)
-// held as B operands in registers for the whole launch. They share a stream of
-// candidate stages (CT codes each) copied from HBM straight into a ring of LDS
-// slots (one copy per work-group) and read back as A operands. Where registers
-// allow two waves on a SIMD (codes up to 320 bits with K <= 64, up to 512 bits
-// with larger K) a fifth wave only streams the stages and publishes a count of
-// landed ones; otherwise the compute waves claim and copy stages themselves.
+// Work split. A work-group has NW compute waves; each owns 16 QG queries
+// (rows) held as B operands in registers for the whole launch. They share a
+// stream of candidate stages (CT codes each) copied from HBM straight into a
+// ring of LDS slots (one copy per work-group) and read back as A operands.
+// With K <= 64 there are 8 compute waves of 32 queries, two on each SIMD: the
+// vector work of one wave (filter, appends, merges, ring bookkeeping) then
+// runs while the other's products keep the matrix core busy, which a single
+// wave per SIMD cannot do. Longer lists take 4 waves (their LDS leaves no room
+// for more). Where registers allow one more wave on a SIMD (codes up to 256
+// bits with K <= 64, up to 512 bits with larger K) an extra wave only streams
+// the stages and publishes a count of landed ones; otherwise the compute waves
+// claim and copy stages themselves.
 //
 // Filter. The accumulator starts at the per-query bias 2 thr - b, so after
 // the contraction acc = 2 (thr - ham): a candidate can enter the list only if
@@ -90,7 +95,7 @@ hipError_t launch_prep(const uint64_t* codes, uint32_t n, uint32_t words, void* 
   return hipGetLastError();
 }
 
-uint32_t run_rows_per_wg(uint32_t K) { return mfma::kWaves * 16u * mfma::qg_of(K); }
+uint32_t run_rows_per_wg(uint32_t K) { return (uint32_t)(mfma::nw_of(K) * 16 * mfma::qg_of(K)); }
 
 hipError_t launch_mfma_batched(const BatchArgs& a, hipStream_t stream) {
   if (a.nitems == 0) return hipSuccess;

@@ -17,7 +17,6 @@ namespace mfma {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void;
 
-constexpr int kWaves = 4;      // waves per work-group
 constexpr int kBuf = 32;       // pending keys per query
 constexpr int kGroupKeys = 16; // keys one query can gain from one 16-code group
 
@@ -90,16 +89,17 @@ __device__ __forceinline__ uint32_t lds_addr(const void* p) {
 }
 
 // Copy one stage (SV4 16-byte chunks, contiguous in HBM) into LDS with the
-// whole work-group: every thread issues (SV4 + 255) / 256 copies (a thread
-// past the end repeats a chunk of the previous round: the same bytes to the
-// same place).
-template <int SV4>
+// NT threads of the work-group: every thread issues (SV4 + NT - 1) / NT copies
+// (a thread past the end repeats a chunk of the previous round: the same
+// bytes to the same place).
+template <int SV4, int NT>
 __device__ __forceinline__ void load_stage(const v4i* __restrict__ src, v4i* dst, uint32_t tid) {
-  constexpr int LPS = (SV4 + 255) / 256;
+  static_assert(NT % 64 == 0 && SV4 % 64 == 0 && SV4 >= NT, "whole waves, one round at least");
+  constexpr int LPS = (SV4 + NT - 1) / NT;
 #pragma unroll
   for (int i = 0; i < LPS; ++i) {
-    uint32_t v = i * 256 + tid;
-    if (SV4 % 256 != 0 && v >= (uint32_t)SV4) v -= 256;
+    uint32_t v = i * NT + tid;
+    if (SV4 % NT != 0 && v >= (uint32_t)SV4) v -= NT;
     dma16(src + v, __builtin_amdgcn_readfirstlane(lds_addr(dst + (v & ~63u))));
   }
 }
@@ -157,11 +157,11 @@ struct TileRing {
 // The copy wave of a work-group with a producer (codes up to 512 bits): it
 // streams the nst stages of the job into the ring and publishes them in order
 // (published = number of stages whose copies are complete), keeping up to D
-// stages in flight; a slot is refilled only after all kWaves compute waves
+// stages in flight; a slot is refilled only after all NW compute waves
 // counted themselves done with its previous stage (freed[slot]). Before it
 // sleeps on a slot it publishes everything it has issued, so that the compute
 // waves never wait on a finished copy.
-template <int SV4, int NST, int D>
+template <int SV4, int NST, int D, int NW>
 __device__ __forceinline__ void produce_stages(TileRing<SV4, NST>& ring, const v4i* __restrict__ src0,
                                                uint32_t nst, uint32_t lane) {
   constexpr int LPS = SV4 / 64;  // copies per lane per stage
@@ -177,7 +177,7 @@ __device__ __forceinline__ void produce_stages(TileRing<SV4, NST>& ring, const v
   for (uint32_t t = 0; t < nst; ++t) {
     const uint32_t slot = t % NST;
     if (t >= (uint32_t)NST) {
-      const uint32_t need = kWaves * (t / NST);
+      const uint32_t need = NW * (t / NST);
       if (__hip_atomic_load(&ring.freed[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <
           need) {
         BDG_WAIT_VMCNT(0);
@@ -199,8 +199,8 @@ __device__ __forceinline__ void produce_stages(TileRing<SV4, NST>& ring, const v
 }
 
 // The work of one work-group on one tile job; q0_wg = first job row of the
-// work-group (the job's rows are split over work-groups of 4 QW rows).
-template <int W, int NR, int QG, int GPS, int NST, bool PROD>
+// work-group (the job's rows are split over work-groups of NW QW rows).
+template <int W, int NR, int QG, int GPS, int NST, bool PROD, int NW>
 __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
                                           const uint64_t* __restrict__ codes, uint32_t K,
                                           uint32_t bits, uint32_t IB, const TileJob& job,
@@ -220,8 +220,8 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
   const int fresh = job.fresh;
   uint32_t* __restrict__ out_idx = job.out_idx;
   uint16_t* __restrict__ out_dist = job.out_dist;
-  uint32_t* lists = state;                    // [kWaves][QW][K]
-  uint32_t* bufs = lists + kWaves * QW * K;   // [kWaves][kBufW]
+  uint32_t* lists = state;                // [NW][QW][K]
+  uint32_t* bufs = lists + NW * QW * K;   // [NW][kBufW]
 
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = tid & 63u;
@@ -253,18 +253,18 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
   }
   if (tid == 0) ring.published = 0;
   if constexpr (PROD) {
-    if (wave == kWaves) {
+    if (wave == NW) {
       lds_barrier();  // the ring words are initialised (pairs with the compute waves' barrier)
       constexpr int LPS = SV4 / 64;
       constexpr int DM = 63 / LPS;
-      produce_stages<SV4, NST, (NST - 1 < DM ? NST - 1 : DM)>(ring, src0, nst, lane);
+      produce_stages<SV4, NST, (NST - 1 < DM ? NST - 1 : DM), NW>(ring, src0, nst, lane);
       return;
     }
   } else {
     if (tid == 0) ring_claimed = NST - 1;
 #pragma unroll
     for (int p = 0; p < NST - 1; ++p)
-      if ((uint32_t)p < nst) load_stage<SV4>(src0 + (size_t)p * SV4, stage[p], tid);
+      if ((uint32_t)p < nst) load_stage<SV4, NW * 64>(src0 + (size_t)p * SV4, stage[p], tid);
   }
 
   // Running lists of the wave's rows (the output rows hold the merge of the
@@ -458,7 +458,7 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
       if (__builtin_amdgcn_readfirstlane(won)) {
         if (t >= (uint32_t)NST)
           while (__hip_atomic_load(&ring_freed[t % NST], __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP) < kWaves * (t / NST))
+                                   __HIP_MEMORY_SCOPE_WORKGROUP) < NW * (t / NST))
             __builtin_amdgcn_s_sleep(1);
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         load_stage_wave<SV4>(src0 + (size_t)t * SV4, stage[t % NST], lane);
@@ -520,43 +520,47 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
   }
 }
 
-// Launch shape per (code words W, list class NR: K <= 64 NR). Where the
-// compute waves' registers leave room for two waves on one SIMD (at most 256
-// each: codes up to 320 bits with 64 queries per wave, up to 512 bits with
-// fewer), a fifth wave is the stage producer; otherwise the compute waves
-// copy the stages themselves.
-constexpr bool use_producer(int W, int NR) { return NR == 1 ? W <= 5 : W <= 8; }
-constexpr int threads_of(int W, int NR) { return (kWaves + (use_producer(W, NR) ? 1 : 0)) * 64; }
+// Launch shape per (code words W, list class NR: K <= 64 NR). Compute waves
+// per work-group and 16-query groups per wave: lists of up to 64 keys take
+// eight waves of 32 queries, two on each SIMD, so that one wave's filter,
+// appends and merges overlap the other's products; longer lists, whose LDS
+// leaves no room for that, four waves. Where the registers leave room for one
+// more wave on a SIMD, an extra wave is the stage producer; otherwise the
+// compute waves copy the stages themselves.
+constexpr int waves_of_nr(int NR) { return NR == 1 ? 8 : 4; }
+constexpr int qgroups_of_nr(int NR) { return NR == 1 ? 2 : (NR == 2 ? 3 : 1); }
+constexpr bool use_producer(int W, int NR) { return NR == 1 ? W <= 4 : W <= 8; }
+constexpr int threads_of(int W, int NR) {
+  return (waves_of_nr(NR) + (use_producer(W, NR) ? 1 : 0)) * 64;
+}
 // 16-code groups per stage (even with a producer, so the ping-pong of
 // accumulators runs across stage boundaries).
 constexpr int stage_groups(int W, int NR) {
   return use_producer(W, NR) ? (W <= 4 ? 4 : 2) : (W <= 5 ? 4 : (W <= 8 ? 2 : 1));
 }
-// Queries per wave / 16.
-constexpr int qgroups_of_nr(int NR) { return NR == 1 ? 4 : (NR == 2 ? 3 : 1); }
-constexpr size_t state_bytes(int K, int qg) {
-  return (size_t)kWaves * ((size_t)16 * qg * K + (size_t)16 * qg * kBuf + 64) * 4;
+constexpr size_t state_bytes(int K, int qg, int nw) {
+  return (size_t)nw * ((size_t)16 * qg * K + (size_t)16 * qg * kBuf + 64) * 4;
 }
 // Stage slots: with a producer as many as the LDS left by the largest lists of
 // the class holds (at most 8); without, the previous fixed depths.
 constexpr int stages_of(int W, int NR) {
   if (!use_producer(W, NR)) return NR == 2 ? 2 : 3;
-  const size_t avail = 160 * 1024 - state_bytes(64 * NR, qgroups_of_nr(NR)) - 256;
+  const size_t avail = 160 * 1024 - state_bytes(64 * NR, qgroups_of_nr(NR), waves_of_nr(NR)) - 256;
   const size_t n = avail / ((size_t)stage_groups(W, NR) * W * 1024);
   return n > 8 ? 8 : (int)n;
 }
 
 // One (row block, column block) tile per launch; work-group g takes rows
-// [256 g, 256 g + 256) of the row block (4 QW = 256 rows at QG = 4).
+// [R g, R g + R) of the row block, R = NW QW.
 template <int W, int NR, int QG, int GPS, int NST>
 __global__ __launch_bounds__(threads_of(W, NR), 1) void knn_mfma_run_kernel(
     const v4i* __restrict__ frags, const uint64_t* __restrict__ codes, uint32_t K, uint32_t bits,
     uint32_t IB, TileJob job) {
   __shared__ TileRing<GPS * W * 64, NST> ring;
   extern __shared__ uint32_t state[];
-  tile_body<W, NR, QG, GPS, NST, use_producer(W, NR)>(frags, codes, K, bits, IB, job,
-                                                      blockIdx.x * (kWaves * 16 * QG), ring,
-                                                      state);
+  constexpr int NW = waves_of_nr(NR);
+  tile_body<W, NR, QG, GPS, NST, use_producer(W, NR), NW>(frags, codes, K, bits, IB, job,
+                                                          blockIdx.x * (NW * 16 * QG), ring, state);
 }
 
 // Many independent partitions in one persistent launch: every work-group
@@ -587,8 +591,8 @@ __global__ __launch_bounds__(threads_of(W, NR), 1) void knn_mfma_batched_kernel(
     job.fresh = 1;
     job.out_idx = out_idx + (size_t)b.row0 * K;
     job.out_dist = out_dist + (size_t)b.row0 * K;
-    tile_body<W, NR, QG, GPS, NST, use_producer(W, NR)>(frags, codes, K, bits, IB, job, 0, ring,
-                                                        state);
+    tile_body<W, NR, QG, GPS, NST, use_producer(W, NR), waves_of_nr(NR)>(frags, codes, K, bits, IB,
+                                                                         job, 0, ring, state);
   }
 }
 
@@ -598,8 +602,9 @@ __global__ void zero_counter_kernel(uint32_t* counter) { *counter = 0; }
 
 inline int nr_of(uint32_t K) { return K <= 64 ? 1 : (K <= 128 ? 2 : 4); }
 inline int qg_of(uint32_t K) { return qgroups_of_nr(nr_of(K)); }
+inline int nw_of(uint32_t K) { return waves_of_nr(nr_of(K)); }
 
-inline size_t run_state_bytes(uint32_t K, int qg) { return state_bytes((int)K, qg); }
+inline size_t run_state_bytes(uint32_t K, int qg) { return state_bytes((int)K, qg, nw_of(K)); }
 
 inline size_t run_lds_bytes(uint32_t W, uint32_t K) {
   const size_t stage = (size_t)stage_groups((int)W, nr_of(K)) * W * 1024;
@@ -617,7 +622,7 @@ inline hipError_t launch_run_w(const RunArgs& a, hipStream_t stream) {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  const uint32_t rows_per_wg = kWaves * 16 * QG;
+  const uint32_t rows_per_wg = waves_of_nr(NR) * 16 * QG;
   dim3 grid((a.nrows + rows_per_wg - 1) / rows_per_wg);
   TileJob job;
   job.row0 = a.row0;
