@@ -90,16 +90,16 @@ __device__ __forceinline__ uint32_t lds_addr(const void* p) {
 
 // Copy one stage (SV4 16-byte chunks, contiguous in HBM) into LDS with the
 // NT threads of the work-group: every thread issues (SV4 + NT - 1) / NT copies
-// (a thread past the end repeats a chunk of the previous round: the same
+// (a wave past the end repeats whole 64-chunk pieces of the stage: the same
 // bytes to the same place).
 template <int SV4, int NT>
 __device__ __forceinline__ void load_stage(const v4i* __restrict__ src, v4i* dst, uint32_t tid) {
-  static_assert(NT % 64 == 0 && SV4 % 64 == 0 && SV4 >= NT, "whole waves, one round at least");
+  static_assert(NT % 64 == 0 && SV4 % 64 == 0, "whole waves");
   constexpr int LPS = (SV4 + NT - 1) / NT;
 #pragma unroll
   for (int i = 0; i < LPS; ++i) {
     uint32_t v = i * NT + tid;
-    if (SV4 % NT != 0 && v >= (uint32_t)SV4) v -= NT;
+    if (SV4 % NT != 0 && v >= (uint32_t)SV4) v %= (uint32_t)SV4;
     dma16(src + v, __builtin_amdgcn_readfirstlane(lds_addr(dst + (v & ~63u))));
   }
 }
@@ -206,7 +206,12 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
                                           uint32_t bits, uint32_t IB, const TileJob& job,
                                           uint32_t q0_wg, TileRing<GPS * W * 64, NST>& ring,
                                           uint32_t* state) {
-  static_assert(!PROD || GPS % 2 == 0, "the producer loop keeps accumulator parity across stages");
+  // Groups contracted together: two where that brings more chains in flight
+  // (QG <= 2) and the stage splits evenly (into an even number of units with
+  // a producer, whose loop keeps the accumulator parity across stages).
+  constexpr int U = (QG <= 2 && GPS % (PROD ? 4 : 2) == 0) ? 2 : 1;
+  constexpr int NU = GPS / U;  // units per stage
+  static_assert(!PROD || NU % 2 == 0, "the producer loop keeps accumulator parity across stages");
   constexpr int QW = 16 * QG;        // queries per wave
   constexpr int CT = 16 * GPS;       // codes per stage
   constexpr int SV4 = GPS * W * 64;  // 16-byte chunks per stage
@@ -330,12 +335,14 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
 
   // Filter of the 16-code group starting at column cs, contracted with the
   // biases bb - bits: append every candidate that beat its query's threshold.
-  auto maxacc = [&](const v4i (&acc)[QG]) {
-    int mx = acc[0][0];
+  auto maxacc = [&](const v4i (&acc)[U][QG]) {
+    int mx = acc[0][0][0];
 #pragma unroll
-    for (int gq = 0; gq < QG; ++gq)
+    for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) mx = max(mx, acc[gq][r]);
+      for (int gq = 0; gq < QG; ++gq)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) mx = max(mx, acc[u][gq][r]);
     return mx;
   };
   auto append = [&](const v4i (&acc)[QG], const int (&bb)[QG], const uint32_t cs) {
@@ -375,46 +382,42 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
     }
   };
 
-  // The contraction of one 16-code group: W layers (one per 64-bit word) of
-  // QG independent products. A scheduling fence after each layer keeps a
-  // chain's consecutive products QG issues apart (never back to back), and
-  // `work(s)` places a share of the vector work inside layer s.
-  auto issue_with = [&](v4i (&acc)[QG], int (&bb)[QG], const v4i (&a)[W], auto&& work) {
+  // Units of U consecutive 16-code groups are contracted together: W layers
+  // (one per 64-bit word) of U QG independent products. A scheduling fence
+  // after each layer keeps a chain's consecutive products U QG issues apart
+  // (never back to back), and `work(s)` places a share of the vector work
+  // inside layer s. With U = 2 (two groups of 2 query tiles) four chains are
+  // in flight, as many as with 4 query tiles.
+  auto issue_with = [&](v4i (&acc)[U][QG], int (&bb)[QG], const v4i (&a)[U][W], auto&& work) {
 #pragma unroll
     for (int s = 0; s < W; ++s) {
 #pragma unroll
-      for (int gq = 0; gq < QG; ++gq)
-        acc[gq] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[s], bq[gq][s],
-                                                        s == 0 ? biasC[gq] : acc[gq], 0, 0, 0);
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int gq = 0; gq < QG; ++gq)
+          acc[u][gq] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[u][s], bq[gq][s],
+                                                             s == 0 ? biasC[gq] : acc[u][gq], 0, 0, 0);
       work(s);
       __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int gq = 0; gq < QG; ++gq) bb[gq] = biasC[gq][0] + (int)bits;
   };
-  auto issue = [&](v4i (&acc)[QG], int (&bb)[QG], const v4i (&a)[W]) {
-    issue_with(acc, bb, a, [](int) {});
-  };
-
-  // Per stage: the contraction of group g is issued before the filter of
-  // group g - 1 (ping-pong accumulators), so the matrix cores keep busy while
-  // the vector ALUs test. A group contracted before a merge tightened a
-  // threshold just admits a superset; its keys use the bias it was contracted
-  // with. The max-reduction of group g - 1 is spread over the layers of
-  // group g's contraction (query group gq in layer gq % W).
-  auto issue_and_test = [&](v4i (&accN)[QG], int (&bbN)[QG], const v4i (&a)[W],
-                            const v4i (&accP)[QG]) {
-    int mx = accP[0][0];
-    issue_with(accN, bbN, a, [&](int s) {
+  auto append_unit = [&](const v4i (&acc)[U][QG], const int (&bb)[QG], const uint32_t cs) {
 #pragma unroll
-      for (int gq = 0; gq < QG; ++gq)
-        if (gq % W == s)
-          mx = max(mx, max(max(accP[gq][0], accP[gq][1]), max(accP[gq][2], accP[gq][3])));
-    });
-    return mx;
+    for (int u = 0; u < U; ++u) append(acc[u], bb, cs + 16 * u);
   };
 
-  v4i acc[2][QG];
+  // Per stage: the contraction of unit j is issued before the filter of unit
+  // j - 1 (ping-pong accumulators), so the matrix cores keep busy while the
+  // vector ALUs test. A unit contracted before a merge tightened a threshold
+  // just admits a superset; its keys use the bias it was contracted with. The
+  // max-reduction of unit j - 1 is spread over the layers of unit j's
+  // contraction (tile u QG + gq in layer (u QG + gq) % W), and so are the
+  // operand reads of unit j + 1 of the same stage: layer s of unit j + 1 is
+  // read into the registers layer s of unit j has just consumed, a whole
+  // unit ahead of its use.
+  v4i acc[2][U][QG];
   int bb[2][QG];
   uint32_t pend = 0xFFFFFFFFu;  // stage this wave copies and has not published
   uint32_t avail = 0;           // with a producer: stages known to have landed
@@ -467,40 +470,58 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
     }
     const v4i* sb = stage[slot];
     const uint32_t cs0 = cstart + st * CT;
-    v4i a[2][W];  // operands of groups g and g + 1 (read one group ahead)
+    v4i a[U][W];  // operands of the unit being contracted (then of the next)
 #pragma unroll
-    for (int s = 0; s < W; ++s) a[0][s] = sb[s * 64 + lane];
-    if (GPS % 2 == 0 && st > 0) {  // last group of stage st - 1
-      if (__any(maxacc(acc[1]) > 0)) append(acc[1], bb[1], cs0 - 16);
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int s = 0; s < W; ++s) a[u][s] = sb[(u * W + s) * 64 + lane];
+    if (NU % 2 == 0 && st > 0) {  // last unit of stage st - 1
+      if (__any(maxacc(acc[1]) > 0)) append_unit(acc[1], bb[1], cs0 - 16 * U);
     }
 #pragma unroll
-    for (int g = 0; g < GPS; ++g) {
-      if (g + 1 < GPS) {
-#pragma unroll
-        for (int s = 0; s < W; ++s) a[(g + 1) & 1][s] = sb[((g + 1) * W + s) * 64 + lane];
-      }
-      if (g + 1 == GPS) {
-        // every operand of the stage is in registers: the slot can be reused
+    for (int j = 0; j < NU; ++j) {
+      if (j + 1 == NU) {
+        // every operand of the stage is in registers or on its way (this
+        // wave's LDS reads complete in order, before the count below): the
+        // slot can be reused
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         if (lane == 0)
           __hip_atomic_fetch_add(&ring_freed[slot], 1u, __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_WORKGROUP);
       }
       __builtin_amdgcn_sched_barrier(0);
-      if (g > 0) {
-        const int mx = issue_and_test(acc[g & 1], bb[g & 1], a[g & 1], acc[(g - 1) & 1]);
-        if (__any(mx > 0)) append(acc[(g - 1) & 1], bb[(g - 1) & 1], cs0 + 16 * (g - 1));
+      // operands of unit j + 1, layer s, once layer s of unit j is issued
+      auto prefetch = [&](int s) {
+        if (j + 1 < NU) {
+#pragma unroll
+          for (int u = 0; u < U; ++u) a[u][s] = sb[((U * (j + 1) + u) * W + s) * 64 + lane];
+        }
+      };
+      if (j > 0) {
+        v4i (&accP)[U][QG] = acc[(j - 1) & 1];
+        int mx = accP[0][0][0];
+        issue_with(acc[j & 1], bb[j & 1], a, [&](int s) {
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int gq = 0; gq < QG; ++gq)
+              if ((u * QG + gq) % W == s)
+                mx = max(mx, max(max(accP[u][gq][0], accP[u][gq][1]),
+                                 max(accP[u][gq][2], accP[u][gq][3])));
+          prefetch(s);
+        });
+        if (__any(mx > 0)) append_unit(accP, bb[(j - 1) & 1], cs0 + 16 * U * (j - 1));
       } else {
-        issue(acc[0], bb[0], a[0]);
+        issue_with(acc[0], bb[0], a, prefetch);
       }
     }
-    if (GPS % 2 != 0) {
-      if (__any(maxacc(acc[(GPS - 1) & 1]) > 0))
-        append(acc[(GPS - 1) & 1], bb[(GPS - 1) & 1], cs0 + 16 * (GPS - 1));
+    if (NU % 2 != 0) {
+      if (__any(maxacc(acc[(NU - 1) & 1]) > 0))
+        append_unit(acc[(NU - 1) & 1], bb[(NU - 1) & 1], cs0 + 16 * U * (NU - 1));
     }
   }
-  if (GPS % 2 == 0 && nst > 0) {
-    if (__any(maxacc(acc[1]) > 0)) append(acc[1], bb[1], cstart + nst * CT - 16);
+  if (NU % 2 == 0 && nst > 0) {
+    if (__any(maxacc(acc[1]) > 0)) append_unit(acc[1], bb[1], cstart + nst * CT - 16 * U);
   }
   BDG_WAIT_VMCNT(0);  // no stage copy of this wave is still in flight
 
