@@ -127,10 +127,12 @@ template <int NR>
 __device__ __forceinline__ int flush_sub(uint32_t* list_q, const uint32_t* buf_q,
                                          uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                          uint32_t K, uint32_t lane, uint32_t IB, uint32_t bits) {
-  const uint32_t t = lane >> 3;
+  static_assert(kBuf == 32, "the pending keys of a query fill lanes 32..63");
+  const uint32_t b = lane - 32u;  // slot of lane 32 + b
+  const uint32_t t = b >> 3;
   const uint32_t ct = t == 0 ? c0 : (t == 1 ? c1 : (t == 2 ? c2 : c3));
-  const uint32_t x = (lane < (uint32_t)kBuf && (lane & (kSub - 1)) < ct) ? buf_q[lane] : kKeyNone;
-  const uint32_t kth = merge_into_list<NR>(list_q, x, K, lane);
+  const uint32_t x = (lane >= 32u && (b & (kSub - 1)) < ct) ? buf_q[b] : kKeyNone;
+  const uint32_t kth = merge_desc_into_list<NR>(list_q, wave_sort_upper32_desc(x, lane), K, lane);
   return kth == kKeyNone ? (int)bits + 2 : 2 * (int)(kth >> IB) - (int)bits;
 }
 

@@ -120,13 +120,25 @@ __device__ __forceinline__ void wave_bitonic_merge(uint32_t (&R)[NR], uint32_t l
   }
 }
 
-// Merge up to 64 new keys (one per lane, any order, kKeyNone for none) into
-// the sorted list of one query (wave-wide; every lane must call it with the
-// same list). Returns the new K-th key (kKeyNone while the list is not full).
+// Up to 32 keys held by lanes 32..63 (lanes 0..31 hold kKeyNone) sorted into
+// a descending sequence over the whole wave: the bitonic network of 32-lane
+// blocks only, whose last stage runs the upper block downwards.
+__device__ __forceinline__ uint32_t wave_sort_upper32_desc(uint32_t x, uint32_t lane) {
+  x = sort_steps<2, 1, false>(x, lane);
+  x = sort_steps<4, 2, false>(x, lane);
+  x = sort_steps<8, 4, false>(x, lane);
+  x = sort_steps<16, 8, false>(x, lane);
+  x = sort_steps<32, 16, false>(x, lane);
+  return x;
+}
+
+// Merge 64 new keys given as a descending sequence over the lanes (kKeyNone
+// for none) into the sorted list of one query (wave-wide; every lane must
+// call it with the same list). Returns the new K-th key (kKeyNone while the
+// list is not full).
 template <int NR>
-__device__ __forceinline__ uint32_t merge_into_list(uint32_t* list_q, uint32_t x, uint32_t K,
-                                                    uint32_t lane) {
-  const uint32_t xr = wave_sort64<true>(x, lane);  // new keys, descending
+__device__ __forceinline__ uint32_t merge_desc_into_list(uint32_t* list_q, uint32_t xr, uint32_t K,
+                                                         uint32_t lane) {
   uint32_t R[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
@@ -148,6 +160,14 @@ __device__ __forceinline__ uint32_t merge_into_list(uint32_t* list_q, uint32_t x
   for (int r = 0; r < NR; ++r)
     if ((last >> 6) == (uint32_t)r) kth = __builtin_amdgcn_readlane(R[r], last & 63);
   return kth;
+}
+
+// Merge up to 64 new keys (one per lane, any order, kKeyNone for none) into
+// the sorted list of one query.
+template <int NR>
+__device__ __forceinline__ uint32_t merge_into_list(uint32_t* list_q, uint32_t x, uint32_t K,
+                                                    uint32_t lane) {
+  return merge_desc_into_list<NR>(list_q, wave_sort64<true>(x, lane), K, lane);
 }
 
 // Merge the c pending keys buf_q[0..c) of one query into its list.
