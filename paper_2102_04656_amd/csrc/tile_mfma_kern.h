@@ -132,7 +132,9 @@ __device__ __forceinline__ int flush_sub(uint32_t* list_q, const uint32_t* buf_q
   const uint32_t t = b >> 3;
   const uint32_t ct = t == 0 ? c0 : (t == 1 ? c1 : (t == 2 ? c2 : c3));
   const uint32_t x = (lane >= 32u && (b & (kSub - 1)) < ct) ? buf_q[b] : kKeyNone;
-  const uint32_t kth = merge_desc_into_list<NR>(list_q, wave_sort_upper32_desc(x, lane), K, lane);
+  uint32_t R[NR];
+  load_list<NR>(list_q, R, K, lane);  // in flight together with the pending keys
+  const uint32_t kth = merge_desc_with<NR>(list_q, R, wave_sort_upper32_desc(x, lane), K, lane);
   return kth == kKeyNone ? (int)bits + 2 : 2 * (int)(kth >> IB) - (int)bits;
 }
 

@@ -34,7 +34,9 @@ __device__ __forceinline__ uint32_t umax32(uint32_t a, uint32_t b) { return a < 
 
 // x of lane (lane ^ M), M a power of two below 64. Masks inside a row of 16
 // lanes use DPP moves (quad permutes for 1 and 2; a row shift each way and a
-// select for 4 and 8), 16 a swizzle inside 32 lanes, 32 a permute.
+// select for 4 and 8); 16 and 32 use the row and half-wave swaps of gfx950
+// (v_permlane16_swap / v_permlane32_swap: the exchange stays in the vector
+// ALU, with no LDS round trip) and a select.
 template <int M>
 __device__ __forceinline__ uint32_t xshfl(uint32_t x, uint32_t lane) {
   if constexpr (M == 1) {
@@ -48,10 +50,14 @@ __device__ __forceinline__ uint32_t xshfl(uint32_t x, uint32_t lane) {
                                                               false);  // lane i <- i - M
     return (lane & M) ? dn : up;
   } else if constexpr (M == 16) {
-    return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x401F);
+    // [0] = odd rows replaced by the even rows, [1] = even rows by the odd
+    const auto s = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    return (lane & 16) ? (uint32_t)s[0] : (uint32_t)s[1];
   } else {
     static_assert(M == 32, "xor mask");
-    return (uint32_t)__shfl_xor((int)x, 32, kWave);
+    // [0] = upper half replaced by the lower, [1] = lower half by the upper
+    const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    return (lane & 32) ? (uint32_t)r[0] : (uint32_t)r[1];
   }
 }
 
@@ -132,19 +138,24 @@ __device__ __forceinline__ uint32_t wave_sort_upper32_desc(uint32_t x, uint32_t 
   return x;
 }
 
-// Merge 64 new keys given as a descending sequence over the lanes (kKeyNone
-// for none) into the sorted list of one query (wave-wide; every lane must
-// call it with the same list). Returns the new K-th key (kKeyNone while the
-// list is not full).
+// The sorted list of one query as NR rows of 64 keys (kKeyNone past K).
 template <int NR>
-__device__ __forceinline__ uint32_t merge_desc_into_list(uint32_t* list_q, uint32_t xr, uint32_t K,
-                                                         uint32_t lane) {
-  uint32_t R[NR];
+__device__ __forceinline__ void load_list(const uint32_t* list_q, uint32_t (&R)[NR], uint32_t K,
+                                          uint32_t lane) {
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     uint32_t p = r * kWave + lane;
     R[r] = (p < K) ? list_q[p] : kKeyNone;
   }
+}
+
+// Merge 64 new keys given as a descending sequence over the lanes (kKeyNone
+// for none) into the sorted list of one query, already loaded as R
+// (wave-wide; every lane must call it with the same list). Returns the new
+// K-th key (kKeyNone while the list is not full).
+template <int NR>
+__device__ __forceinline__ uint32_t merge_desc_with(uint32_t* list_q, uint32_t (&R)[NR], uint32_t xr,
+                                                    uint32_t K, uint32_t lane) {
   // min(list[i], new_padded[N-1-i]) keeps the N smallest of the union as a
   // bitonic sequence; only the last 64 positions meet real new keys.
   R[NR - 1] = umin32(R[NR - 1], xr);
@@ -167,7 +178,9 @@ __device__ __forceinline__ uint32_t merge_desc_into_list(uint32_t* list_q, uint3
 template <int NR>
 __device__ __forceinline__ uint32_t merge_into_list(uint32_t* list_q, uint32_t x, uint32_t K,
                                                     uint32_t lane) {
-  return merge_desc_into_list<NR>(list_q, wave_sort64<true>(x, lane), K, lane);
+  uint32_t R[NR];
+  load_list<NR>(list_q, R, K, lane);
+  return merge_desc_with<NR>(list_q, R, wave_sort64<true>(x, lane), K, lane);
 }
 
 // Merge the c pending keys buf_q[0..c) of one query into its list.
