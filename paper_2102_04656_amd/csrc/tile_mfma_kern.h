@@ -150,21 +150,37 @@ struct TileJob {
   uint16_t* out_dist;
 };
 
+constexpr int kMaxWaves = 8;  // compute waves of a work-group, at most
+
 // LDS of a tile besides the lists: the stage ring and its control words.
 template <int SV4, int NST>
 struct TileRing {
   v4i stage[NST][SV4];
-  uint32_t landed[NST], freed[NST], claimed;
-  uint32_t published;  // with a producer: stages below this count have landed
+  uint32_t landed[NST], claimed;
+  uint32_t done[kMaxWaves];  // done[w] = stages compute wave w has read completely
+  uint32_t published;        // with a producer: stages below this count have landed
 };
+
+// Whether every one of the NW compute waves has read all stages below `need`
+// (one LDS read per lane for lanes < NW, wave-wide; the caller's lanes all
+// take part).
+template <int NW, int SV4, int NST>
+__device__ __forceinline__ bool stages_read(TileRing<SV4, NST>& ring, uint32_t need, uint32_t lane) {
+  static_assert(NW <= kMaxWaves, "done counters");
+  const uint32_t d = lane < (uint32_t)NW
+                         ? __hip_atomic_load(&ring.done[lane], __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_WORKGROUP)
+                         : 0xFFFFFFFFu;
+  return __ballot(d < need) == 0;
+}
 
 // The copy wave of a work-group with a producer (codes up to 512 bits): it
 // streams the nst stages of the job into the ring and publishes them in order
 // (published = number of stages whose copies are complete), keeping up to D
-// stages in flight; a slot is refilled only after all NW compute waves
-// counted themselves done with its previous stage (freed[slot]). Before it
-// sleeps on a slot it publishes everything it has issued, so that the compute
-// waves never wait on a finished copy.
+// stages in flight; a slot is refilled only after all NW compute waves have
+// read its previous stage (their done counters). Before it sleeps on a slot
+// it publishes everything it has issued, so that the compute waves never wait
+// on a finished copy.
 template <int SV4, int NST, int D, int NW>
 __device__ __forceinline__ void produce_stages(TileRing<SV4, NST>& ring, const v4i* __restrict__ src0,
                                                uint32_t nst, uint32_t lane) {
@@ -181,14 +197,11 @@ __device__ __forceinline__ void produce_stages(TileRing<SV4, NST>& ring, const v
   for (uint32_t t = 0; t < nst; ++t) {
     const uint32_t slot = t % NST;
     if (t >= (uint32_t)NST) {
-      const uint32_t need = NW * (t / NST);
-      if (__hip_atomic_load(&ring.freed[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <
-          need) {
+      const uint32_t need = t - NST + 1;  // the slot's previous stage is t - NST
+      if (!stages_read<NW>(ring, need, lane)) {
         BDG_WAIT_VMCNT(0);
         publish_upto(t);
-        while (__hip_atomic_load(&ring.freed[slot], __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_WORKGROUP) < need)
-          __builtin_amdgcn_s_sleep(1);
+        while (!stages_read<NW>(ring, need, lane)) __builtin_amdgcn_s_sleep(1);
       }
     }
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -222,7 +235,6 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
   constexpr int kBufW = QW * kBuf + 64;  // + a discard slot per lane
   auto& stage = ring.stage;
   auto& ring_landed = ring.landed;
-  auto& ring_freed = ring.freed;
   auto& ring_claimed = ring.claimed;
   const uint32_t row0 = job.row0, nrows = job.nrows, cb = job.cb, ce = job.ce;
   const uint32_t colbase = job.colbase;
@@ -250,16 +262,15 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
   // Stage ring control. The compute waves move through the stages
   // independently (a wave that merges lists does not hold the others back),
   // within the slack the ring allows: landed[b] = 1 + generation of the last
-  // stage whose copy into slot b completed; freed[b] counts the (wave, stage)
-  // pairs done reading slot b. With a producer wave, that wave does every
+  // stage whose copy into slot b completed; done[w] counts the stages compute
+  // wave w has read completely (one plain store per wave and stage; whoever
+  // refills a slot checks all of them). With a producer wave, that wave does every
   // copy (produce_stages). Without one, claimed = next stage to be copied: the
   // first compute wave to reach a stage start claims the copy of the stage
   // NST - 1 ahead, issues it (the whole stage) once every wave has finished
   // the slot's previous stage, and publishes it at its next stage start.
-  if (tid < NST) {
-    ring_landed[tid] = (!PROD && tid < NST - 1) ? 1u : 0u;  // prologue copies
-    ring_freed[tid] = 0;
-  }
+  if (tid < NST) ring_landed[tid] = (!PROD && tid < NST - 1) ? 1u : 0u;  // prologue copies
+  if (tid < kMaxWaves) ring.done[tid] = 0;
   if (tid == 0) ring.published = 0;
   if constexpr (PROD) {
     if (wave == NW) {
@@ -464,9 +475,7 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
       }
       if (__builtin_amdgcn_readfirstlane(won)) {
         if (t >= (uint32_t)NST)
-          while (__hip_atomic_load(&ring_freed[t % NST], __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP) < NW * (t / NST))
-            __builtin_amdgcn_s_sleep(1);
+          while (!stages_read<NW>(ring, t - NST + 1, lane)) __builtin_amdgcn_s_sleep(1);
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         load_stage_wave<SV4>(src0 + (size_t)t * SV4, stage[t % NST], lane);
         pend = t;
@@ -490,8 +499,8 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
         // slot can be reused
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         if (lane == 0)
-          __hip_atomic_fetch_add(&ring_freed[slot], 1u, __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+          __hip_atomic_store(&ring.done[wave], st + 1, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
       }
       __builtin_amdgcn_sched_barrier(0);
       // operands of unit j + 1, layer s, once layer s of unit j is issued
