@@ -17,6 +17,10 @@ Contents
                              merge-sort of the second reduce, Sec. 3.2 / 3.3).
   * ``knn_sharded_rows``  -- the definition applied per shard, local indices.
   * ``pair_distances``    -- Hamming distance of explicit pairs.
+  * ``propagate``         -- one round of neighbourhood propagation (Sec. 3.3):
+                             top-K of a row's list and its neighbours' lists.
+  * ``propagate_filtered``-- the same with the paper's propagation filter
+                             (Sec. 3.6 (3)) applied to the second floor.
 Floating-point parts (the binarisers, the float-kNN ground truth, the encoder
 network, its loss and optimiser) live in ``oracle.learned``.
 """
@@ -197,3 +201,76 @@ def knn_sharded_rows(codes: np.ndarray, offsets, K: int, shard: int, rows=None):
     """kNN rows of one shard; ``rows`` are shard-local row ids."""
     lo, hi = int(offsets[shard]), int(offsets[shard + 1])
     return knn_rows(codes[lo:hi], K, rows=rows)
+
+
+# --------------------------------------------------------------------------
+# Neighbourhood propagation (one more floor of neighbours)
+# --------------------------------------------------------------------------
+
+def _ham_row(codes: np.ndarray, x: int, cols) -> dict:
+    """{j: Hamming distance of codes x and j} by per-word XOR and bit count."""
+    out = {}
+    for j in cols:
+        out[j] = sum(bin(int(a) ^ int(b)).count("1") for a, b in zip(codes[x], codes[j]))
+    return out
+
+
+def _floors(in_idx: np.ndarray, n: int, x: int):
+    first = [int(j) for j in in_idx[x] if int(j) != NO_IDX and int(j) < n]
+    second = []
+    for y in first:
+        second += [int(z) for z in in_idx[y] if int(z) != NO_IDX and int(z) < n]
+    return first, second
+
+
+def propagate(codes: np.ndarray, in_idx: np.ndarray, K: int):
+    """One round of neighbourhood propagation (Sec. 3.3), the plain definition.
+
+    The flat, depth-one breadth-first step: row x compares itself with every
+    neighbour of its first-floor neighbours (the second floor) and keeps, from
+    its own list and that floor, the K smallest distinct (ham(x, z), z) with
+    z != x, ascending, sentinel-padded. Distances are recomputed from the codes
+    (the input distances are not used). Entries equal to 0xFFFFFFFF or >= n
+    are absent. Small inputs only (pure Python).
+    """
+    codes = np.ascontiguousarray(codes, dtype=np.uint64)
+    in_idx = np.asarray(in_idx, dtype=np.uint32)
+    n = codes.shape[0]
+    out_idx = np.full((n, K), NO_IDX, dtype=np.uint32)
+    out_dist = np.full((n, K), NO_DIST, dtype=np.uint16)
+    for x in range(n):
+        first, second = _floors(in_idx, n, x)
+        cand = (set(first) | set(second)) - {x}
+        d = _ham_row(codes, x, cand)
+        for k, (dd, j) in enumerate(sorted((d[j], j) for j in cand)[:K]):
+            out_idx[x, k] = j
+            out_dist[x, k] = dd
+    return out_idx, out_dist
+
+
+def propagate_filtered(codes: np.ndarray, in_idx: np.ndarray, K: int):
+    """As ``propagate``, with the propagation filter (Sec. 3.6 (3)): a
+    second-floor candidate of x is dropped when its distance exceeds the
+    largest distance between x and its first-floor neighbours (the reading
+    taken: drop when strictly larger, keep ties, so that a tie at that distance
+    with a smaller index can still enter). With K first-floor neighbours the
+    filter cannot change the result; the tests check that it does not."""
+    codes = np.ascontiguousarray(codes, dtype=np.uint64)
+    in_idx = np.asarray(in_idx, dtype=np.uint32)
+    n = codes.shape[0]
+    out_idx = np.full((n, K), NO_IDX, dtype=np.uint32)
+    out_dist = np.full((n, K), NO_DIST, dtype=np.uint16)
+    for x in range(n):
+        first, second = _floors(in_idx, n, x)
+        first = [j for j in first if j != x]
+        d1 = _ham_row(codes, x, set(first))
+        full = len(set(first)) >= K
+        maxd = max(d1.values()) if (full and d1) else None
+        d2 = _ham_row(codes, x, set(second) - {x} - set(first))
+        kept = {j: v for j, v in d2.items() if maxd is None or v <= maxd}
+        allc = dict(d1)
+        allc.update(kept)
+        for k, (dd, j) in enumerate(sorted((v, j) for j, v in allc.items())[:K]):
+            out_idx[x, k] = j
+            out_dist[x, k] = dd
+    return out_idx, out_dist
