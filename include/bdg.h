@@ -126,6 +126,30 @@ int bdg_merge_lists(const uint32_t *in_idx, const uint16_t *in_dist, uint32_t n,
                     uint32_t K_in, uint32_t K, uint32_t *out_idx, uint16_t *out_dist,
                     void *stream);
 
+/*
+ * One round of neighbourhood propagation (Sec. 3.3): every row is compared
+ * with all neighbours of its first-floor neighbours (the second floor), and
+ * keeps the K nearest of its own list and that floor.
+ *   codes    [n][bits/64] uint64, device (bits a multiple of 64, at most
+ *            BDG_MAX_BITS)
+ *   in_idx   [n][K] uint32, device: row r's neighbours, any order; entries
+ *            equal to BDG_NO_IDX, >= n or equal to r are absent. Only the
+ *            indices are read: every distance is recomputed from the codes.
+ *   out_idx/out_dist [n][K], device, must not overlap in_idx
+ * Row r of the output = the K smallest distinct (ham(r, z), z), z != r, over
+ * z in in_idx[r] and in in_idx[y] for every y in in_idx[r], ascending,
+ * sentinel-padded (BDG_NO_IDX, BDG_NO_DIST). The propagation filter of
+ * Sec. 3.6 (3) (a second-floor candidate farther than the row's current K-th
+ * distance is not merged; ties are) is applied inside and never changes the
+ * result. An exact graph is returned unchanged. Enqueued on `stream`; the
+ * caller owns every buffer. Errors: BDG_EINVAL (bits not a multiple of 64,
+ * K = 0, null pointer, overlapping outputs), BDG_EUNSUPPORTED (bits or K
+ * beyond the maxima, n = 2^32 - 1), BDG_EDEVICE (launch failure); outputs are
+ * untouched on validation errors. n = 0 is a no-op.
+ */
+int bdg_propagate(const uint64_t *codes, uint32_t n, uint32_t bits, uint32_t K,
+                  const uint32_t *in_idx, uint32_t *out_idx, uint16_t *out_dist, void *stream);
+
 /* ---------------------------------------------------- many partitions --- */
 
 /*

@@ -208,11 +208,12 @@ def knn_sharded_rows(codes: np.ndarray, offsets, K: int, shard: int, rows=None):
 # --------------------------------------------------------------------------
 
 def _ham_row(codes: np.ndarray, x: int, cols) -> dict:
-    """{j: Hamming distance of codes x and j} by per-word XOR and bit count."""
-    out = {}
-    for j in cols:
-        out[j] = sum(bin(int(a) ^ int(b)).count("1") for a, b in zip(codes[x], codes[j]))
-    return out
+    """{j: Hamming distance of codes x and j} (the C pair routine)."""
+    cols = sorted(cols)
+    if not cols:
+        return {}
+    d = pair_distances(codes, np.full(len(cols), x, dtype=np.uint32), np.array(cols, dtype=np.uint32))
+    return dict(zip(cols, d.tolist()))
 
 
 def _floors(in_idx: np.ndarray, n: int, x: int):

@@ -113,6 +113,7 @@ _SIGS = {
     "bdg_build_knn_ex": [_p, _u32, _u32, _u32, _p, _p, _p, _p],
     "bdg_build_knn_workspace_size": [_u32, _u32, _u32, _p, _p],
     "bdg_merge_lists": [_p, _p, _u32, _u32, _u32, _u32, _p, _p, _p],
+    "bdg_propagate": [_p, _u32, _u32, _u32, _p, _p, _p, _p],
     "bdg_batch_plan_create": [_p, _u32, _u32, _u32, _p, _p],
     "bdg_batch_plan_destroy": [_p],
     "bdg_batch_plan_info": [_p, _p],
@@ -212,6 +213,11 @@ def bdg_merge_lists(in_idx, in_dist, n, L, K_in, K, out_idx, out_dist, stream=No
                                  _ptr(out_dist), _stream(stream))
 
 
+def bdg_propagate(codes, n, bits, K, in_idx, out_idx, out_dist, stream=None) -> int:
+    return lib().bdg_propagate(_ptr(codes), n, bits, K, _ptr(in_idx), _ptr(out_idx),
+                               _ptr(out_dist), _stream(stream))
+
+
 def bdg_status_string(status: int) -> str:
     return lib().bdg_status_string(status).decode()
 
@@ -246,6 +252,19 @@ def merge_lists(in_idx, in_dist, K: int, stream=None):
     out = (torch.empty((n, K), dtype=torch.int32, device=in_idx.device),
            torch.empty((n, K), dtype=torch.int16, device=in_idx.device))
     _check(bdg_merge_lists(in_idx, in_dist, n, L, kin, K, out[0], out[1], stream))
+    return out
+
+
+def propagate(codes, in_idx, bits: int | None = None, stream=None):
+    """One round of neighbourhood propagation of the graph ``in_idx [n][K]``
+    (GPU tensors; codes ``[n][bits/64]`` int64/uint64). Returns new
+    ``(idx int32 [n][K], dist int16 [n][K])``."""
+    import torch
+    n, K = in_idx.shape
+    bits = bits or codes.shape[1] * 64
+    out = (torch.empty((n, K), dtype=torch.int32, device=in_idx.device),
+           torch.empty((n, K), dtype=torch.int16, device=in_idx.device))
+    _check(bdg_propagate(codes, n, bits, K, in_idx, out[0], out[1], stream))
     return out
 
 

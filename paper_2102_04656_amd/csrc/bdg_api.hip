@@ -311,4 +311,31 @@ int bdg_merge_lists(const uint32_t* in_idx, const uint16_t* in_dist, uint32_t n,
   return BDG_OK;
 }
 
+int bdg_propagate(const uint64_t* codes, uint32_t n, uint32_t bits, uint32_t K,
+                  const uint32_t* in_idx, uint32_t* out_idx, uint16_t* out_dist, void* stream) {
+  g_last_error.clear();
+  if (bits == 0 || bits % 64 != 0)
+    return set_error(BDG_EINVAL, "bits must be a positive multiple of 64 (got %u)", bits);
+  if (bits > BDG_MAX_BITS) return set_error(BDG_EUNSUPPORTED, "bits > %u", BDG_MAX_BITS);
+  if (K == 0) return set_error(BDG_EINVAL, "K must be >= 1");
+  if (K > BDG_MAX_K) return set_error(BDG_EUNSUPPORTED, "K > %u", BDG_MAX_K);
+  if (n == 0xFFFFFFFFu) return set_error(BDG_EUNSUPPORTED, "n must be < 2^32 - 1");
+  if (n == 0) return BDG_OK;
+  if (!codes || !in_idx || !out_idx || !out_dist)
+    return set_error(BDG_EINVAL, "null device pointer");
+  const uintptr_t ib = reinterpret_cast<uintptr_t>(in_idx);
+  const uintptr_t ie = ib + (uintptr_t)n * K * sizeof(uint32_t);
+  const uintptr_t ob = reinterpret_cast<uintptr_t>(out_idx);
+  const uintptr_t oe = ob + (uintptr_t)n * K * sizeof(uint32_t);
+  const uintptr_t db = reinterpret_cast<uintptr_t>(out_dist);
+  const uintptr_t de = db + (uintptr_t)n * K * sizeof(uint16_t);
+  if ((ob < ie && ib < oe) || (db < ie && ib < de))
+    return set_error(BDG_EINVAL, "outputs overlap in_idx (rows read other rows' lists)");
+  (void)hipGetLastError();
+  hipError_t e = bdg::launch_propagate(codes, n, bits / 64, K, in_idx, out_idx, out_dist,
+                                       reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_error(e, "propagate launch");
+  return BDG_OK;
+}
+
 }  // extern "C"

@@ -34,6 +34,14 @@ hipError_t launch_merge(const uint32_t* in_idx, const uint16_t* in_dist, uint32_
                         uint32_t K_in, uint32_t K, uint32_t* out_idx, uint16_t* out_dist,
                         int dedup, hipStream_t stream);
 
+// One round of neighbourhood propagation (propagate.hip): row r of out =
+// the K nearest distinct entries of r's list in in_idx and of the lists of
+// its entries (distances recomputed from the codes). in_idx and out must not
+// overlap.
+hipError_t launch_propagate(const uint64_t* codes, uint32_t n, uint32_t words, uint32_t K,
+                            const uint32_t* in_idx, uint32_t* out_idx, uint16_t* out_dist,
+                            hipStream_t stream);
+
 // Running-merge tile on the int8 matrix cores (tile_mfma.hip). One launch
 // merges columns [cb, ce) into the lists of rows [row0, row0 + nrows); the
 // lists live in out_idx/out_dist (row r at (r - row0) * K), which hold the

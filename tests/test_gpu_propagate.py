@@ -1,0 +1,74 @@
+"""Neighbourhood propagation on the GPU (``bdg_propagate``) against the CPU
+oracle: bit-exact graphs on seeded inputs (several code lengths and list
+classes, ragged and holed lists), the exact graph as a fixed point at the
+size of the 20k x 128-bit workload, and the error paths of the entry point."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2102_04656_amd import bdg, datagen
+from tests.test_oracle_propagate import approx_graph
+
+pytestmark = pytest.mark.gpu
+
+NO_IDX = oracle.NO_IDX
+
+
+def gpu_propagate(codes, in_idx):
+    import torch
+    c = torch.from_numpy(np.ascontiguousarray(codes).view(np.int64)).cuda()
+    g = torch.from_numpy(np.ascontiguousarray(in_idx).view(np.int32)).cuda()
+    oi, od = bdg.propagate(c, g, bits=codes.shape[1] * 64)
+    torch.cuda.synchronize()
+    return bdg.to_numpy_graph(oi, od)
+
+
+@pytest.mark.parametrize("n,bits,centres,K,keep,seed", [
+    (1200, 128, 30, 16, 0.5, 11),   # one 64-lane chunk per list, 2 words
+    (900, 256, 20, 64, 0.4, 12),    # full 64-entry lists, 4 words
+    (700, 64, 15, 100, 0.3, 13),    # two rows of keys (K > 64), 1 word
+    (500, 192, 10, 5, 0.6, 14),     # short lists, 3 words
+    (400, 512, 8, 33, 0.2, 15),     # ragged K, 8 words
+])
+def test_propagate_matches_oracle(n, bits, centres, K, keep, seed):
+    print(f"[propagate] n={n} bits={bits} K={K} seed={seed}", flush=True)
+    codes = datagen.clustered_codes(n, bits, centres, 0.2, seed)
+    gi, _ = approx_graph(codes, K, seed, keep=keep)
+    ei, ed = oracle.propagate(codes, gi, K)
+    pi, pd = gpu_propagate(codes, gi)
+    assert np.array_equal(pi, ei)
+    assert np.array_equal(pd, ed)
+
+
+def test_propagate_holes_self_and_out_of_range():
+    n, K = 600, 24
+    codes = datagen.clustered_codes(n, 128, 12, 0.2, 16)
+    gi, _ = approx_graph(codes, K, 16, keep=0.5)
+    gi[::4, K - 5:] = NO_IDX            # short lists
+    gi[1::7, 0] = n + 123               # out of range
+    gi[2::9, 1] = np.arange(n)[2::9]    # the row itself
+    gi[3::11, 2] = gi[3::11, 3]         # a repeated entry
+    ei, ed = oracle.propagate(codes, gi, K)
+    pi, pd = gpu_propagate(codes, gi)
+    assert np.array_equal(pi, ei) and np.array_equal(pd, ed)
+
+
+def test_exact_graph_is_fixed_point_20k():
+    w = datagen.WORKLOADS["clustered-20k-128b-k32"]
+    codes = datagen.clustered_codes(w["n"], w["bits"], w["n_centres"], w["p"], w["seed"])
+    ei, ed = oracle.knn_rows(codes, w["K"])
+    pi, pd = gpu_propagate(codes, ei)
+    assert np.array_equal(pi, ei) and np.array_equal(pd, ed)
+
+
+def test_propagate_errors():
+    import torch
+    c = torch.zeros((8, 2), dtype=torch.int64, device="cuda")
+    g = torch.zeros((8, 4), dtype=torch.int32, device="cuda")
+    oi = torch.empty((8, 4), dtype=torch.int32, device="cuda")
+    od = torch.empty((8, 4), dtype=torch.int16, device="cuda")
+    assert bdg.bdg_propagate(c, 8, 100, 4, g, oi, od) == bdg.BDG_EINVAL
+    assert bdg.bdg_propagate(c, 8, 128, 0, g, oi, od) == bdg.BDG_EINVAL
+    assert bdg.bdg_propagate(c, 8, 2048, 4, g, oi, od) == bdg.BDG_EUNSUPPORTED
+    assert bdg.bdg_propagate(c, 8, 128, 4, g, g, od) == bdg.BDG_EINVAL  # in place
+    assert bdg.bdg_propagate(c, 0, 128, 4, g, oi, od) == bdg.BDG_OK
