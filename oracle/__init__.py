@@ -224,7 +224,7 @@ def _floors(in_idx: np.ndarray, n: int, x: int):
     return first, second
 
 
-def propagate(codes: np.ndarray, in_idx: np.ndarray, K: int):
+def propagate(codes: np.ndarray, in_idx: np.ndarray, K: int, rows=None):
     """One round of neighbourhood propagation (Sec. 3.3), the plain definition.
 
     The flat, depth-one breadth-first step: row x compares itself with every
@@ -232,20 +232,22 @@ def propagate(codes: np.ndarray, in_idx: np.ndarray, K: int):
     its own list and that floor, the K smallest distinct (ham(x, z), z) with
     z != x, ascending, sentinel-padded. Distances are recomputed from the codes
     (the input distances are not used). Entries equal to 0xFFFFFFFF or >= n
-    are absent. Small inputs only (pure Python).
+    are absent. ``rows`` (optional) selects output rows: the result then has
+    one row per entry of ``rows``. Small inputs or row samples only.
     """
     codes = np.ascontiguousarray(codes, dtype=np.uint64)
     in_idx = np.asarray(in_idx, dtype=np.uint32)
     n = codes.shape[0]
-    out_idx = np.full((n, K), NO_IDX, dtype=np.uint32)
-    out_dist = np.full((n, K), NO_DIST, dtype=np.uint16)
-    for x in range(n):
+    rows = np.arange(n) if rows is None else np.asarray(rows)
+    out_idx = np.full((rows.size, K), NO_IDX, dtype=np.uint32)
+    out_dist = np.full((rows.size, K), NO_DIST, dtype=np.uint16)
+    for r, x in enumerate(rows.tolist()):
         first, second = _floors(in_idx, n, x)
         cand = (set(first) | set(second)) - {x}
         d = _ham_row(codes, x, cand)
         for k, (dd, j) in enumerate(sorted((d[j], j) for j in cand)[:K]):
-            out_idx[x, k] = j
-            out_dist[x, k] = dd
+            out_idx[r, k] = j
+            out_dist[r, k] = dd
     return out_idx, out_dist
 
 

@@ -9,20 +9,27 @@
 //
 // One wave per row; the row's code stays in registers. Every distance is
 // recomputed from the codes (the input lists are read for their indices
-// only). The running result R (64 NR keys dist << 32 | idx, ascending, as in
-// the list merge) starts with the row's own list; each 64-entry chunk of a
-// neighbour's list becomes 64 candidates, and only a chunk in which some
-// candidate passes the filter is merged in: drop entries already in R
-// (binary search of R in LDS) and repeats inside the chunk, then the bitonic
-// merge. The filter is the propagation filter of Sec. 3.6 (3) applied
+// only). Neighbours of neighbours repeat a lot (points of one cluster sit in
+// each other's lists), so before a candidate's code is gathered its index is
+// entered in a per-wave hash set in LDS (linear probing, compare-and-swap):
+// only the first occurrence of an index is measured. The running result R
+// (64 NR keys dist << 32 | idx, ascending, as in the list merge) starts with
+// the row's own list; each 64-entry chunk of a neighbour's list becomes up
+// to 64 new candidates, and only a chunk in which some candidate passes the
+// filter is merged in. While every index of the row has been recorded in the
+// set, new candidates are distinct from each other and from R; once an
+// insertion gives up (the probe limit), the row falls back to dropping
+// entries already in R (binary search of R in LDS) and repeats inside a
+// chunk before the bitonic merge. The filter is the propagation filter of Sec. 3.6 (3) applied
 // continuously: a candidate farther than the current K-th distance of R
 // cannot enter (ties are kept, since a smaller index may still displace the
 // K-th key), and R's K-th distance only decreases, so the result is the
 // exact top-K of the union of both floors.
 //
-// Bound: random gathers of codes (8 bytes per word per candidate, K^2
-// candidates per row) and of list rows; memory latency is hidden by many
-// resident waves (few registers, 512 NR bytes of LDS per wave).
+// Bound: random gathers of list rows and of the codes of distinct
+// candidates (8 bytes per word, a cache line per code); memory latency is
+// hidden by many resident waves (few registers, 8 KB + 512 NR bytes of LDS
+// per wave).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -36,6 +43,24 @@ namespace {
 constexpr int kPW = 64;
 constexpr uint32_t kMaxWords = 16;
 constexpr uint32_t kAbsent = 0xFFFFFFFFu;
+constexpr uint32_t kSetBits = 11;  // hash set of 2048 indices per wave
+constexpr uint32_t kSetSize = 1u << kSetBits;
+constexpr int kProbes = 8;
+
+// Insert z into the set: 1 = new, 0 = already there, 2 = not recorded (every
+// probed slot held another index).
+__device__ __forceinline__ uint32_t set_insert(uint32_t* set, uint32_t z) {
+  uint32_t slot = (z * 0x9E3779B1u) >> (32 - kSetBits);
+  for (int i = 0; i < kProbes; ++i) {
+    uint32_t expect = kAbsent;
+    if (__hip_atomic_compare_exchange_strong(&set[slot], &expect, z, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+      return 1u;
+    if (expect == z) return 0u;
+    slot = (slot + 1) & (kSetSize - 1);
+  }
+  return 2u;
+}
 
 template <int NR>
 __global__ __launch_bounds__(256) void propagate_kernel(const uint64_t* __restrict__ codes,
@@ -44,12 +69,20 @@ __global__ __launch_bounds__(256) void propagate_kernel(const uint64_t* __restri
                                                         uint32_t* __restrict__ out_idx,
                                                         uint16_t* __restrict__ out_dist) {
   __shared__ uint64_t lds[4][kPW * NR];
+  __shared__ uint32_t sets[4][kSetSize];
   const uint32_t wave = threadIdx.x >> 6;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t row = blockIdx.x * 4 + wave;
   if (row >= n) return;  // wave-uniform
   uint64_t* Rl = lds[wave];
+  uint32_t* set = sets[wave];
   constexpr uint32_t N = kPW * NR;
+#pragma unroll
+  for (uint32_t i = 0; i < kSetSize / kPW; ++i) set[i * kPW + lane] = kAbsent;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  bool exact_set = true;  // wave-uniform: every index so far is in the set
 
   uint64_t xw[kMaxWords];
 #pragma unroll
@@ -65,8 +98,13 @@ __global__ __launch_bounds__(256) void propagate_kernel(const uint64_t* __restri
   uint64_t R[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) R[r] = kNone64;
-  // Merge up to 64 candidate keys (one per lane, kNone64 for none) into R.
-  auto absorb = [&](uint64_t x) {
+  // Merge up to 64 candidate keys (one per lane, kNone64 for none) into R;
+  // with dedup, keys already in R and repeats among them are dropped first.
+  auto absorb = [&](uint64_t x, bool dedup) {
+    if (!dedup) {
+      merge64_into<NR>(R, x, lane);
+      return;
+    }
     x = wave_sort64_u64(x, lane);
 #pragma unroll
     for (int r = 0; r < NR; ++r) Rl[r * kPW + lane] = R[r];
@@ -113,10 +151,13 @@ __global__ __launch_bounds__(256) void propagate_kernel(const uint64_t* __restri
   for (int r = 0; r < NR; ++r) {
     const uint32_t p = r * kPW + lane;
     const uint32_t y = p < K ? in_idx[base + p] : kAbsent;
-    const bool ok = y != kAbsent && y < n && y != row;
+    const bool valid = y != kAbsent && y < n && y != row;
+    const uint32_t ins = valid ? set_insert(set, y) : 0u;
+    if (__any(ins == 2u)) exact_set = false;
+    const bool ok = ins != 0u;  // first occurrence (or not recorded)
     yv[r] = ok ? y : kAbsent;
     const uint64_t key = ok ? (((uint64_t)ham_to(y) << 32) | y) : kNone64;
-    if (__any(ok)) absorb(key);
+    if (__any(ok)) absorb(key, !exact_set);
   }
   uint32_t maxd = kth_dist();
 
@@ -132,11 +173,14 @@ __global__ __launch_bounds__(256) void propagate_kernel(const uint64_t* __restri
       for (uint32_t c0 = 0; c0 < K; c0 += kPW) {
         const uint32_t p = c0 + lane;
         const uint32_t z = p < K ? in_idx[ybase + p] : kAbsent;
-        const bool ok = z != kAbsent && z < n && z != row;
+        const bool valid = z != kAbsent && z < n && z != row;
+        const uint32_t ins = valid ? set_insert(set, z) : 0u;
+        if (__any(ins == 2u)) exact_set = false;
+        const bool ok = ins != 0u;
         const uint32_t h = ok ? ham_to(z) : 0xFFFFFFFFu;
         const bool pass = ok && h <= maxd;
         if (!__any(pass)) continue;
-        absorb(pass ? (((uint64_t)h << 32) | z) : kNone64);
+        absorb(pass ? (((uint64_t)h << 32) | z) : kNone64, !exact_set);
         maxd = kth_dist();
       }
     }

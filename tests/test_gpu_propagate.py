@@ -40,6 +40,24 @@ def test_propagate_matches_oracle(n, bits, centres, K, keep, seed):
     assert np.array_equal(pd, ed)
 
 
+@pytest.mark.parametrize("n,bits,K,keep,seed", [
+    (5000, 128, 100, 0.2, 21),
+    (3000, 64, 200, 0.1, 22),
+])
+def test_propagate_candidate_set_overflow(n, bits, K, keep, seed):
+    """More distinct candidates per row than the kernel's per-wave index set
+    holds (2048): rows fall back to deduplicating against the running list.
+    Checked on a seeded row sample."""
+    print(f"[propagate overflow] n={n} bits={bits} K={K} seed={seed}", flush=True)
+    codes = datagen.clustered_codes(n, bits, 40, 0.2, seed)
+    gi, _ = approx_graph(codes, K, seed, keep=keep)
+    rows = np.sort(np.random.default_rng(seed).choice(n, size=120, replace=False))
+    ei, ed = oracle.propagate(codes, gi, K, rows=rows)
+    pi, pd = gpu_propagate(codes, gi)
+    assert np.array_equal(pi[rows], ei)
+    assert np.array_equal(pd[rows], ed)
+
+
 def test_propagate_holes_self_and_out_of_range():
     n, K = 600, 24
     codes = datagen.clustered_codes(n, 128, 12, 0.2, 16)
