@@ -21,6 +21,9 @@ Contents
                              top-K of a row's list and its neighbours' lists.
   * ``propagate_filtered``-- the same with the paper's propagation filter
                              (Sec. 3.6 (3)) applied to the second floor.
+  * ``bkmeans``, ``nearest_centres``, ``dac_graph`` -- the single-pass
+                             divide-and-conquer (Sec. 3.2): binary centres,
+                             budgeted multi-assignment, partition search.
 Floating-point parts (the binarisers, the float-kNN ground truth, the encoder
 network, its loss and optimiser) live in ``oracle.learned``.
 """
@@ -276,4 +279,95 @@ def propagate_filtered(codes: np.ndarray, in_idx: np.ndarray, K: int):
         for k, (dd, j) in enumerate(sorted((v, j) for j, v in allc.items())[:K]):
             out_idx[x, k] = j
             out_dist[x, k] = dd
+    return out_idx, out_dist
+
+
+# --------------------------------------------------------------------------
+# Single-pass divide-and-conquer (Sec. 3.2): binary k-means centres, each
+# point's nearest centres under the coarse_num budget, and the search of
+# every point against the home members of its selected centres
+# --------------------------------------------------------------------------
+
+def _ham_matrix(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """[len(a)][len(b)] Hamming distances by per-word XOR and a byte table."""
+    table = np.array([bin(v).count("1") for v in range(256)], dtype=np.int32)
+    out = np.zeros((a.shape[0], b.shape[0]), dtype=np.int32)
+    for w in range(a.shape[1]):
+        x = np.bitwise_xor(a[:, w][:, None], b[:, w][None, :])
+        out += table[x.view(np.uint8).reshape(x.shape + (8,))].sum(axis=2)
+    return out
+
+
+def bkmeans(codes: np.ndarray, sample, init, iters: int) -> np.ndarray:
+    """Binary k-means on the rows ``sample`` of ``codes`` (Sec. 3.2, Eq. 1-2).
+
+    Centres start as the codes of rows ``init`` (m of them). Each iteration:
+    assign every sample point to its nearest centre (Hamming; ties to the
+    smaller centre index), then set bit b of centre j to 1 iff more than half
+    of its points have bit b set (the majority form of c_j = sgn(sum x_i) on
+    binary members; a tie gives 0); a centre with no point keeps its bits.
+    """
+    codes = np.ascontiguousarray(codes, dtype=np.uint64)
+    S = codes[np.asarray(sample, dtype=np.int64)]
+    C = codes[np.asarray(init, dtype=np.int64)].copy()
+    W = codes.shape[1]
+    bits = np.unpackbits(S.view(np.uint8), axis=1, bitorder="little").astype(np.int64)
+    for _ in range(iters):
+        D = _ham_matrix(S, C)
+        home = np.argmin(D, axis=1)  # first minimum: the smaller index
+        for j in range(C.shape[0]):
+            members = bits[home == j]
+            if members.shape[0] == 0:
+                continue
+            ones = members.sum(axis=0)
+            newbits = (2 * ones > members.shape[0]).astype(np.uint8)
+            C[j] = np.packbits(newbits, bitorder="little").view(np.uint64)[:W]
+    return C
+
+
+def nearest_centres(codes: np.ndarray, centres: np.ndarray, T: int):
+    """Per point the T nearest centres, ascending by (distance, centre)."""
+    D = _ham_matrix(np.ascontiguousarray(codes, dtype=np.uint64),
+                    np.ascontiguousarray(centres, dtype=np.uint64))
+    m = D.shape[1]
+    order = np.lexsort((np.broadcast_to(np.arange(m), D.shape), D), axis=1)[:, :T]
+    return order.astype(np.uint32), np.take_along_axis(D, order, axis=1).astype(np.uint16)
+
+
+def dac_graph(codes: np.ndarray, centres: np.ndarray, T: int, coarse_num: int, K: int,
+              rows=None):
+    """The approximate kNN graph of the single-pass divide-and-conquer.
+
+    Home of a point = its nearest centre; D_j = the points whose home is j.
+    Point q selects its nearest centres in order, adding centre j and |D_j|
+    to a running total and stopping once the total reaches coarse_num (the
+    centre that crosses the budget is included), at most T centres. Its row
+    = the K smallest (ham(q, b), b), b != q, over b in the union of D_j of the
+    selected centres (disjoint sets, so the second reduce has nothing to
+    deduplicate), sentinel-padded. ``rows`` selects output rows.
+    """
+    codes = np.ascontiguousarray(codes, dtype=np.uint64)
+    n = codes.shape[0]
+    top, _ = nearest_centres(codes, centres, T)
+    home = top[:, 0].astype(np.int64)
+    size = np.bincount(home, minlength=centres.shape[0])
+    members = [np.nonzero(home == j)[0] for j in range(centres.shape[0])]
+    rows = np.arange(n) if rows is None else np.asarray(rows)
+    out_idx = np.full((rows.size, K), NO_IDX, dtype=np.uint32)
+    out_dist = np.full((rows.size, K), NO_DIST, dtype=np.uint16)
+    for r, q in enumerate(rows.tolist()):
+        cand, total = [], 0
+        for j in top[q].tolist():
+            cand.append(members[j])
+            total += int(size[j])
+            if total >= coarse_num:
+                break
+        c = np.concatenate(cand)
+        c = c[c != q]
+        if c.size == 0:
+            continue
+        d = pair_distances(codes, np.full(c.size, q, dtype=np.uint32), c.astype(np.uint32))
+        order = np.lexsort((c, d))[:K]
+        out_idx[r, : order.size] = c[order]
+        out_dist[r, : order.size] = d[order]
     return out_idx, out_dist
