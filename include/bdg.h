@@ -150,6 +150,45 @@ int bdg_merge_lists(const uint32_t *in_idx, const uint16_t *in_dist, uint32_t n,
 int bdg_propagate(const uint64_t *codes, uint32_t n, uint32_t bits, uint32_t K,
                   const uint32_t *in_idx, uint32_t *out_idx, uint16_t *out_dist, void *stream);
 
+/*
+ * Binary k-means centres for the single-pass divide-and-conquer (Sec. 3.2,
+ * Eq. 1-2), run on a down-sample.
+ *   codes    [n][bits/64] uint64, device
+ *   sample   host array of ns row indices (< n): the down-sample
+ *   init     host array of m row indices (< n): the starting centres
+ *   iters    rounds of: each sample row joins its nearest centre (ties to the
+ *            smaller centre index); bit b of a centre becomes 1 iff more than
+ *            half of its rows have bit b set (a tie gives 0); a centre
+ *            without rows keeps its bits
+ *   centres  [m][bits/64] uint64, device, written
+ * Scratch is allocated on `stream` and freed before return; the call returns
+ * after the work completes. Errors: BDG_EINVAL (bits, m = 0, null pointer, an
+ * index >= n), BDG_EUNSUPPORTED (bits > BDG_MAX_BITS, m > 2^20), BDG_ENOMEM,
+ * BDG_EDEVICE.
+ */
+int bdg_bkmeans(const uint64_t *codes, uint32_t n, uint32_t bits, const uint32_t *sample,
+                uint32_t ns, const uint32_t *init, uint32_t m, uint32_t iters,
+                uint64_t *centres, void *stream);
+
+/*
+ * Approximate kNN graph of the single-pass divide-and-conquer (Sec. 3.2).
+ * Home of a row = its nearest centre (ties to the smaller index); D_j = the
+ * rows whose home is j. Row q takes its nearest centres in order (at most T),
+ * adding |D_j| to a running total and stopping once it reaches coarse_num
+ * (the centre that crosses the budget is included), and its output row is
+ * the K smallest (ham(q, b), b), b != q, over the home rows of those centres,
+ * ascending, sentinel-padded. With T >= m and coarse_num >= n this is the
+ * exact graph.
+ *   codes [n][bits/64], centres [m][bits/64] uint64, device
+ *   out_idx [n][K] uint32, out_dist [n][K] uint16, device
+ * T in 1..64, K in 1..BDG_MAX_K, m in 1..2^20, coarse_num >= 1. Scratch
+ * (about n (4 T + 4 + bits/8) bytes) is allocated and freed on `stream`
+ * (stream-ordered). Errors as bdg_build_knn_ex; BDG_EUNSUPPORTED for T > 64.
+ */
+int bdg_build_knn_dac(const uint64_t *codes, uint32_t n, uint32_t bits, const uint64_t *centres,
+                      uint32_t m, uint32_t T, uint32_t coarse_num, uint32_t K, uint32_t *out_idx,
+                      uint16_t *out_dist, void *stream);
+
 /* ---------------------------------------------------- many partitions --- */
 
 /*

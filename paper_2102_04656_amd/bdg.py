@@ -114,6 +114,8 @@ _SIGS = {
     "bdg_build_knn_workspace_size": [_u32, _u32, _u32, _p, _p],
     "bdg_merge_lists": [_p, _p, _u32, _u32, _u32, _u32, _p, _p, _p],
     "bdg_propagate": [_p, _u32, _u32, _u32, _p, _p, _p, _p],
+    "bdg_bkmeans": [_p, _u32, _u32, _p, _u32, _p, _u32, _u32, _p, _p],
+    "bdg_build_knn_dac": [_p, _u32, _u32, _p, _u32, _u32, _u32, _u32, _p, _p, _p],
     "bdg_batch_plan_create": [_p, _u32, _u32, _u32, _p, _p],
     "bdg_batch_plan_destroy": [_p],
     "bdg_batch_plan_info": [_p, _p],
@@ -265,6 +267,34 @@ def propagate(codes, in_idx, bits: int | None = None, stream=None):
     out = (torch.empty((n, K), dtype=torch.int32, device=in_idx.device),
            torch.empty((n, K), dtype=torch.int16, device=in_idx.device))
     _check(bdg_propagate(codes, n, bits, K, in_idx, out[0], out[1], stream))
+    return out
+
+
+def bkmeans(codes, sample, init, iters: int, bits: int | None = None, stream=None):
+    """Binary k-means centres (GPU): ``sample`` and ``init`` are host arrays of
+    row indices; returns a ``[m][bits/64]`` int64 GPU tensor."""
+    import numpy as np
+    import torch
+    n = codes.shape[0]
+    bits = bits or codes.shape[1] * 64
+    s = np.ascontiguousarray(sample, dtype=np.uint32)
+    i = np.ascontiguousarray(init, dtype=np.uint32)
+    out = torch.empty((i.size, bits // 64), dtype=torch.int64, device=codes.device)
+    _check(lib().bdg_bkmeans(_ptr(codes), n, bits, s.ctypes.data, s.size, i.ctypes.data, i.size,
+                             iters, _ptr(out), _stream(stream)))
+    return out
+
+
+def build_knn_dac(codes, centres, K: int, T: int, coarse_num: int, bits: int | None = None,
+                  stream=None):
+    """Approximate graph of the single-pass divide-and-conquer (GPU tensors)."""
+    import torch
+    n = codes.shape[0]
+    bits = bits or codes.shape[1] * 64
+    out = (torch.empty((n, K), dtype=torch.int32, device=codes.device),
+           torch.empty((n, K), dtype=torch.int16, device=codes.device))
+    _check(lib().bdg_build_knn_dac(_ptr(codes), n, bits, _ptr(centres), centres.shape[0], T,
+                                   coarse_num, K, _ptr(out[0]), _ptr(out[1]), _stream(stream)))
     return out
 
 

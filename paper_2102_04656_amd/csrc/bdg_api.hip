@@ -338,4 +338,83 @@ int bdg_propagate(const uint64_t* codes, uint32_t n, uint32_t bits, uint32_t K,
   return BDG_OK;
 }
 
+int bdg_bkmeans(const uint64_t* codes, uint32_t n, uint32_t bits, const uint32_t* sample,
+                uint32_t ns, const uint32_t* init, uint32_t m, uint32_t iters,
+                uint64_t* centres, void* stream) {
+  g_last_error.clear();
+  if (bits == 0 || bits % 64 != 0)
+    return set_error(BDG_EINVAL, "bits must be a positive multiple of 64 (got %u)", bits);
+  if (bits > BDG_MAX_BITS) return set_error(BDG_EUNSUPPORTED, "bits > %u", BDG_MAX_BITS);
+  if (m == 0) return set_error(BDG_EINVAL, "m must be >= 1");
+  if (m > (1u << 20)) return set_error(BDG_EUNSUPPORTED, "m > 2^20");
+  if (!codes || !init || !centres || (ns > 0 && !sample))
+    return set_error(BDG_EINVAL, "null pointer");
+  for (uint32_t j = 0; j < m; ++j)
+    if (init[j] >= n) return set_error(BDG_EINVAL, "init[%u] = %u is not a row (n = %u)", j, init[j], n);
+  for (uint32_t i = 0; i < ns; ++i)
+    if (sample[i] >= n)
+      return set_error(BDG_EINVAL, "sample[%u] = %u is not a row (n = %u)", i, sample[i], n);
+  const uint32_t words = bits / 64;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
+  const size_t b_s = (size_t)(ns ? ns : 1) * 4, b_i = (size_t)m * 4, b_h = b_s,
+               b_c = (size_t)m * words * 64 * 4, b_z = (size_t)m * 4;
+  char* ws = nullptr;
+  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&ws), b_s + b_i + b_h + b_c + b_z, st);
+  if (e != hipSuccess) return set_error(BDG_ENOMEM, "scratch: %s", hipGetErrorString(e));
+  uint32_t* d_sample = reinterpret_cast<uint32_t*>(ws);
+  uint32_t* d_init = reinterpret_cast<uint32_t*>(ws + b_s);
+  uint32_t* d_home = reinterpret_cast<uint32_t*>(ws + b_s + b_i);
+  uint32_t* d_cnt = reinterpret_cast<uint32_t*>(ws + b_s + b_i + b_h);
+  uint32_t* d_size = reinterpret_cast<uint32_t*>(ws + b_s + b_i + b_h + b_c);
+  if (ns) e = hipMemcpyAsync(d_sample, sample, (size_t)ns * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_init, init, b_i, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = bdg::launch_bkmeans(codes, words, d_sample, ns, d_init, m, iters, centres, d_home, d_cnt,
+                            d_size, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);  // host index arrays are read by the copies
+  hipError_t f = hipFreeAsync(ws, st);
+  if (e != hipSuccess) return device_error(e, "bkmeans");
+  if (f != hipSuccess) return device_error(f, "bkmeans scratch");
+  return BDG_OK;
+}
+
+int bdg_build_knn_dac(const uint64_t* codes, uint32_t n, uint32_t bits, const uint64_t* centres,
+                      uint32_t m, uint32_t T, uint32_t coarse_num, uint32_t K, uint32_t* out_idx,
+                      uint16_t* out_dist, void* stream) {
+  g_last_error.clear();
+  if (bits == 0 || bits % 64 != 0)
+    return set_error(BDG_EINVAL, "bits must be a positive multiple of 64 (got %u)", bits);
+  if (bits > BDG_MAX_BITS) return set_error(BDG_EUNSUPPORTED, "bits > %u", BDG_MAX_BITS);
+  if (K == 0 || m == 0 || T == 0 || coarse_num == 0)
+    return set_error(BDG_EINVAL, "K, m, T and coarse_num must be >= 1");
+  if (K > BDG_MAX_K) return set_error(BDG_EUNSUPPORTED, "K > %u", BDG_MAX_K);
+  if (T > 64) return set_error(BDG_EUNSUPPORTED, "T > 64");
+  if (m > (1u << 20)) return set_error(BDG_EUNSUPPORTED, "m > 2^20");
+  if (n == 0xFFFFFFFFu) return set_error(BDG_EUNSUPPORTED, "n must be < 2^32 - 1");
+  if (n == 0) return BDG_OK;
+  if (!codes || !centres || !out_idx || !out_dist) return set_error(BDG_EINVAL, "null pointer");
+  const uint32_t words = bits / 64;
+  const uint32_t Te = T < m ? T : m;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
+  const size_t b_top = (size_t)n * Te * 4, b_m = ((size_t)m + 1) * 4, b_n = (size_t)n * 4,
+               b_hc = (size_t)n * words * 8;
+  char* ws = nullptr;
+  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&ws), b_hc + b_top + 3 * b_m + b_n, st);
+  if (e != hipSuccess) return set_error(BDG_ENOMEM, "scratch: %s", hipGetErrorString(e));
+  uint64_t* hcodes = reinterpret_cast<uint64_t*>(ws);
+  uint32_t* top = reinterpret_cast<uint32_t*>(ws + b_hc);
+  uint32_t* size = reinterpret_cast<uint32_t*>(ws + b_hc + b_top);
+  uint32_t* off = reinterpret_cast<uint32_t*>(ws + b_hc + b_top + b_m);
+  uint32_t* cursor = reinterpret_cast<uint32_t*>(ws + b_hc + b_top + 2 * b_m);
+  uint32_t* member = reinterpret_cast<uint32_t*>(ws + b_hc + b_top + 3 * b_m);
+  e = bdg::launch_dac(codes, n, words, centres, m, Te, coarse_num, K, top, size, off, cursor,
+                      member, hcodes, out_idx, out_dist, st);
+  hipError_t f = hipFreeAsync(ws, st);
+  if (e != hipSuccess) return device_error(e, "dac launch");
+  if (f != hipSuccess) return device_error(f, "dac scratch");
+  return BDG_OK;
+}
+
 }  // extern "C"

@@ -42,6 +42,21 @@ hipError_t launch_propagate(const uint64_t* codes, uint32_t n, uint32_t words, u
                             const uint32_t* in_idx, uint32_t* out_idx, uint16_t* out_dist,
                             hipStream_t stream);
 
+// Single-pass divide-and-conquer (dac.hip). launch_bkmeans: centres =
+// codes of rows init[0..m), then `iters` rounds of assignment of the rows
+// sample[0..ns) and majority update (device scratch: home [ns], cnt
+// [m][words][64], size [m]). launch_dac: the approximate graph (device
+// scratch: top [n][T], size [m], off [m + 1], cursor [m], member [n],
+// hcodes [n][words]). Row indices in sample / init must be < n.
+hipError_t launch_bkmeans(const uint64_t* codes, uint32_t words, const uint32_t* sample,
+                          uint32_t ns, const uint32_t* init, uint32_t m, uint32_t iters,
+                          uint64_t* centres, uint32_t* home, uint32_t* cnt, uint32_t* size,
+                          hipStream_t stream);
+hipError_t launch_dac(const uint64_t* codes, uint32_t n, uint32_t words, const uint64_t* centres,
+                      uint32_t m, uint32_t T, uint32_t coarse_num, uint32_t K, uint32_t* top,
+                      uint32_t* size, uint32_t* off, uint32_t* cursor, uint32_t* member,
+                      uint64_t* hcodes, uint32_t* out_idx, uint16_t* out_dist, hipStream_t stream);
+
 // Running-merge tile on the int8 matrix cores (tile_mfma.hip). One launch
 // merges columns [cb, ce) into the lists of rows [row0, row0 + nrows); the
 // lists live in out_idx/out_dist (row r at (r - row0) * K), which hold the
