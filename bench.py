@@ -258,12 +258,7 @@ def propagation_leg(codes, codes_dev, exact, bits, K, with_oracle, steps=3):
     ms = float(np.mean(times))
 
     def recall(gr):
-        hits = 0
-        for r0 in range(0, n, 65536):
-            a = gr[r0:r0 + 65536].long()
-            b = exact[r0:r0 + 65536].long()
-            hits += int((a[:, :, None] == b[:, None, :]).any(dim=2).sum().item())
-        return hits / (n * K)
+        return graph_recall(gr, exact)
 
     words = bits // 64
     cand = K + K * K  # first and second floor per row
@@ -289,6 +284,70 @@ def propagation_leg(codes, codes_dev, exact, bits, K, with_oracle, steps=3):
                                "cores": 1, "kind": "oracle", "seconds": t,
                                "sample": f"{rows.size} seeded rows of the same input graph"}
         res["parity_on_sample"] = bool(np.array_equal(gi[rows], oi) and np.array_equal(gd[rows], od))
+    return res
+
+
+def graph_recall(graph, exact):
+    """Mean over rows of |graph row ∩ exact row| / K (GPU tensors, chunked)."""
+    n, K = exact.shape
+    hits = 0
+    for r0 in range(0, n, 65536):
+        a = graph[r0:r0 + 65536].long()
+        b = exact[r0:r0 + 65536].long()
+        hits += int((a[:, :, None] == b[:, None, :]).any(dim=2).sum().item())
+    return hits / (n * K)
+
+
+def dac_leg(codes_dev, exact, bits, K, m=1024, iters=8, T=16, coarse_num=8192):
+    """The paper's construction pipeline on the workload's codes (Sec. 3.2 then
+    3.3): binary k-means centres on a 10 % seeded sample, the approximate graph
+    of the single-pass divide-and-conquer, then one round of neighbourhood
+    propagation; recall@K of each graph against the exact one and the time of
+    each step. Parity of these steps with the oracle is covered by the tests
+    (the oracle's nearest-centre step over all rows is too slow here)."""
+    import torch
+    from paper_2102_04656_amd import bdg
+    n = exact.shape[0]
+    g = np.random.default_rng(2103)
+    sample = np.sort(g.choice(n, size=n // 10, replace=False)).astype(np.uint32)
+    init = sample[np.sort(g.choice(sample.size, size=m, replace=False))]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    C = bdg.bkmeans(codes_dev, sample, init, iters, bits=bits)
+    torch.cuda.synchronize()
+    t_bk = (time.perf_counter() - t0) * 1e3
+    gi, _ = bdg.build_knn_dac(codes_dev, C, K, T, coarse_num, bits=bits)  # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    gi, gd = bdg.build_knn_dac(codes_dev, C, K, T, coarse_num, bits=bits)
+    e1.record()
+    torch.cuda.synchronize()
+    t_dac = e0.elapsed_time(e1)
+    e0.record()
+    pi, pd = bdg.propagate(codes_dev, gi, bits=bits)
+    e1.record()
+    torch.cuda.synchronize()
+    t_prop = e0.elapsed_time(e1)
+    res = {"centres": m, "sample_rows": int(sample.size), "kmeans_iters": iters, "T": T,
+           "coarse_num": coarse_num, "K": K,
+           "kmeans_ms": t_bk, "dac_ms": t_dac, "propagate_ms": t_prop,
+           "recall_dac": graph_recall(gi, exact), "recall_dac_propagated": graph_recall(pi, exact),
+           "parity": "tests/test_gpu_dac.py and tests/test_gpu_propagate.py (oracle, n <= 20k)"}
+    sweep = []
+    for cn in (512, 1024, 2048, 4096):  # the candidate budget against recall (Sec. 4.5)
+        e0.record()
+        gi, _ = bdg.build_knn_dac(codes_dev, C, K, T, cn, bits=bits)
+        e1.record()
+        torch.cuda.synchronize()
+        td = e0.elapsed_time(e1)
+        e0.record()
+        pi, _ = bdg.propagate(codes_dev, gi, bits=bits)
+        e1.record()
+        torch.cuda.synchronize()
+        sweep.append({"coarse_num": cn, "dac_ms": td, "recall_dac": graph_recall(gi, exact),
+                      "propagate_ms": e0.elapsed_time(e1), "recall_propagated": graph_recall(pi, exact)})
+    res["coarse_num_sweep"] = sweep
     return res
 
 
@@ -401,6 +460,9 @@ def main():
     ap.add_argument("--propagate", action=argparse.BooleanOptionalAction, default=True,
                     help="after the timed builds, run one round of neighbourhood propagation "
                          "from a degraded copy of the graph (reported, not the value)")
+    ap.add_argument("--dac", action=argparse.BooleanOptionalAction, default=True,
+                    help="after the timed builds, run the divide-and-conquer pipeline (binary "
+                         "k-means, approximate graph, one propagation round) and report recall")
     ap.add_argument("--recall", action=argparse.BooleanOptionalAction, default=True,
                     help="after the timed builds, train the learned encoder on the 1M x 512 "
                          "mixture and report recall@64 of learned vs SRP codes (~30 s)")
@@ -507,6 +569,13 @@ def main():
                                                 with_oracle=not args.no_cpu_baseline)
         log(f"[bench] propagation: {result['propagation']['ms']:.2f} ms, recall "
             f"{result['propagation']['recall_in']:.3f} -> {result['propagation']['recall_out']:.3f}")
+    if args.dac:
+        log("[bench] divide-and-conquer leg")
+        result["dac"] = dac_leg(codes_dev, outs[0], bits, K)
+        d = result["dac"]
+        log(f"[bench] dac: kmeans {d['kmeans_ms']:.1f} ms, graph {d['dac_ms']:.1f} ms (recall "
+            f"{d['recall_dac']:.3f}), + propagation {d['propagate_ms']:.1f} ms (recall "
+            f"{d['recall_dac_propagated']:.3f})")
     if args.recall:
         del outs, codes_dev
         result["recall"] = recall_leg()
