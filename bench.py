@@ -335,7 +335,8 @@ def dac_leg(codes_dev, exact, bits, K, m=1024, iters=8, T=16, coarse_num=8192):
            "recall_dac": graph_recall(gi, exact), "recall_dac_propagated": graph_recall(pi, exact),
            "parity": "tests/test_gpu_dac.py and tests/test_gpu_propagate.py (oracle, n <= 20k)"}
     sweep = []
-    for cn in (512, 1024, 2048, 4096):  # the candidate budget against recall (Sec. 4.5)
+    for cn in (coarse_num // 16, coarse_num // 8, coarse_num // 4, coarse_num // 2):
+        # the candidate budget against recall (Sec. 4.5)
         e0.record()
         gi, _ = bdg.build_knn_dac(codes_dev, C, K, T, cn, bits=bits)
         e1.record()
@@ -571,7 +572,11 @@ def main():
             f"{result['propagation']['recall_in']:.3f} -> {result['propagation']['recall_out']:.3f}")
     if args.dac:
         log("[bench] divide-and-conquer leg")
-        result["dac"] = dac_leg(codes_dev, outs[0], bits, K)
+        # m is the knob the paper tunes (Sec. 4.5): on these synthetic codes recall needs
+        # about as many centres as true clusters (1,000 at 1M rows; 20,000 at 4M rows)
+        big = n > 2_000_000
+        result["dac"] = dac_leg(codes_dev, outs[0], bits, K, m=32768 if big else 1024,
+                                T=32 if big else 16, coarse_num=4096 if big else 8192)
         d = result["dac"]
         log(f"[bench] dac: kmeans {d['kmeans_ms']:.1f} ms, graph {d['dac_ms']:.1f} ms (recall "
             f"{d['recall_dac']:.3f}), + propagation {d['propagate_ms']:.1f} ms (recall "
