@@ -359,8 +359,10 @@ int bdg_bkmeans(const uint64_t* codes, uint32_t n, uint32_t bits, const uint32_t
   (void)hipGetLastError();
   const size_t b_s = (size_t)(ns ? ns : 1) * 4, b_i = (size_t)m * 4, b_h = b_s,
                b_c = (size_t)m * words * 64 * 4, b_z = (size_t)m * 4;
+  const size_t b_main = (b_s + b_i + b_h + b_c + b_z + 255) & ~size_t(255);
+  const size_t b_t = bdg::bkmeans_tile_scratch_bytes(ns, m, words);
   char* ws = nullptr;
-  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&ws), b_s + b_i + b_h + b_c + b_z, st);
+  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&ws), b_main + b_t, st);
   if (e != hipSuccess) return set_error(BDG_ENOMEM, "scratch: %s", hipGetErrorString(e));
   uint32_t* d_sample = reinterpret_cast<uint32_t*>(ws);
   uint32_t* d_init = reinterpret_cast<uint32_t*>(ws + b_s);
@@ -371,7 +373,7 @@ int bdg_bkmeans(const uint64_t* codes, uint32_t n, uint32_t bits, const uint32_t
   if (e == hipSuccess) e = hipMemcpyAsync(d_init, init, b_i, hipMemcpyHostToDevice, st);
   if (e == hipSuccess)
     e = bdg::launch_bkmeans(codes, words, d_sample, ns, d_init, m, iters, centres, d_home, d_cnt,
-                            d_size, st);
+                            d_size, b_t ? ws + b_main : nullptr, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);  // host index arrays are read by the copies
   hipError_t f = hipFreeAsync(ws, st);
   if (e != hipSuccess) return device_error(e, "bkmeans");
@@ -400,8 +402,10 @@ int bdg_build_knn_dac(const uint64_t* codes, uint32_t n, uint32_t bits, const ui
   (void)hipGetLastError();
   const size_t b_top = (size_t)n * Te * 4, b_m = ((size_t)m + 1) * 4, b_n = (size_t)n * 4,
                b_hc = (size_t)n * words * 8;
+  const size_t b_ts = bdg::dac_top_scratch_bytes(n, m, words, Te);
+  const size_t b_main = (b_hc + b_top + 3 * b_m + b_n + 255) & ~size_t(255);
   char* ws = nullptr;
-  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&ws), b_hc + b_top + 3 * b_m + b_n, st);
+  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&ws), b_main + b_ts, st);
   if (e != hipSuccess) return set_error(BDG_ENOMEM, "scratch: %s", hipGetErrorString(e));
   uint64_t* hcodes = reinterpret_cast<uint64_t*>(ws);
   uint32_t* top = reinterpret_cast<uint32_t*>(ws + b_hc);
@@ -410,7 +414,7 @@ int bdg_build_knn_dac(const uint64_t* codes, uint32_t n, uint32_t bits, const ui
   uint32_t* cursor = reinterpret_cast<uint32_t*>(ws + b_hc + b_top + 2 * b_m);
   uint32_t* member = reinterpret_cast<uint32_t*>(ws + b_hc + b_top + 3 * b_m);
   e = bdg::launch_dac(codes, n, words, centres, m, Te, coarse_num, K, top, size, off, cursor,
-                      member, hcodes, out_idx, out_dist, st);
+                      member, hcodes, out_idx, out_dist, b_ts ? ws + b_main : nullptr, st);
   hipError_t f = hipFreeAsync(ws, st);
   if (e != hipSuccess) return device_error(e, "dac launch");
   if (f != hipSuccess) return device_error(f, "dac scratch");

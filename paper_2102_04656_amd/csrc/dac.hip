@@ -15,10 +15,12 @@
 // centres, so the partitions' lists never need a merge: the sets are
 // disjoint and one running top-K per point receives them all.
 //
-// Kernels: sample assignment with the centres staged in LDS (one thread per
-// point); bit counts with atomics and the majority update; the T nearest
-// centres per point (one wave per point, 64 centres per step, the 64-bit
-// wave merge); sizes, offsets and the scatter into home order; the search
+// Kernels: sample assignment on the matrix cores (rectangular tile, K = 1),
+// or with the centres staged in LDS (one thread per point); bit counts with atomics and the majority update; the T nearest
+// centres per point on the matrix cores (the running-list tile of
+// tile_mfma.hip in its rectangular mode: rows = the codes, columns = the
+// centres), or one wave per point on the vector ALUs where the tile does not
+// take the shape; sizes, offsets and the scatter into home order; the search
 // (one wave per point, coalesced member codes, a filter against the running
 // K-th distance before each merge).
 #include <hip/hip_runtime.h>
@@ -256,16 +258,57 @@ inline dim3 grid_of(size_t threads) { return dim3((unsigned)((threads + 255) / 2
 
 }  // namespace
 
+size_t bkmeans_tile_scratch_bytes(uint32_t ns, uint32_t m, uint32_t words) {
+  if (ns == 0 || !run_supported(m, words, 1)) return 0;
+  return (((size_t)ns * words * 8 + 255) & ~size_t(255)) +
+         ((prep_bytes(m, words) + 255) & ~size_t(255)) + (size_t)ns * sizeof(uint16_t);
+}
+
 hipError_t launch_bkmeans(const uint64_t* codes, uint32_t words, const uint32_t* sample,
                           uint32_t ns, const uint32_t* init, uint32_t m, uint32_t iters,
                           uint64_t* centres, uint32_t* home, uint32_t* cnt, uint32_t* size,
-                          hipStream_t stream) {
+                          void* tile_scratch, hipStream_t stream) {
   if (words == 0 || words > kDMaxWords || m == 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(bk_init_kernel, grid_of((size_t)m * words), dim3(256), 0, stream, codes,
                      words, init, m, centres);
+  // With scratch, the assignment runs on the matrix cores: the sample's codes
+  // are gathered once into rows, and each round the centres become the
+  // columns of a rectangular tile with K = 1 ((distance, centre) order: ties
+  // to the smaller centre).
+  const bool tile = tile_scratch != nullptr && ns > 0 && run_supported(m, words, 1);
+  uint64_t* scode = static_cast<uint64_t*>(tile_scratch);
+  char* frags = tile ? static_cast<char*>(tile_scratch) + (((size_t)ns * words * 8 + 255) & ~size_t(255))
+                     : nullptr;
+  uint16_t* tdist = tile ? reinterpret_cast<uint16_t*>(frags + ((prep_bytes(m, words) + 255) & ~size_t(255)))
+                         : nullptr;
+  if (tile)
+    hipLaunchKernelGGL(bk_init_kernel, grid_of((size_t)ns * words), dim3(256), 0, stream, codes,
+                       words, sample, ns, scode);
   for (uint32_t it = 0; it < iters && ns > 0; ++it) {
-    hipLaunchKernelGGL(bk_assign_kernel, grid_of(ns), dim3(256), 0, stream, codes, words, sample,
-                       ns, centres, m, home);
+    if (tile) {
+      hipError_t e = launch_prep(centres, m, words, frags, stream);
+      if (e != hipSuccess) return e;
+      RunArgs a;
+      a.codes = scode;
+      a.frags = frags;
+      a.words = words;
+      a.bits = words * 64;
+      a.K = 1;
+      a.idx_bits = run_idx_bits(words * 64);
+      a.row0 = 0;
+      a.nrows = ns;
+      a.cb = 0;
+      a.ce = m;
+      a.fresh = 1;
+      a.out_idx = home;
+      a.out_dist = tdist;
+      a.rect = 1;
+      e = launch_mfma_run(a, stream);
+      if (e != hipSuccess) return e;
+    } else {
+      hipLaunchKernelGGL(bk_assign_kernel, grid_of(ns), dim3(256), 0, stream, codes, words, sample,
+                         ns, centres, m, home);
+    }
     hipError_t e = hipMemsetAsync(cnt, 0, (size_t)m * words * 64 * sizeof(uint32_t), stream);
     if (e != hipSuccess) return e;
     e = hipMemsetAsync(size, 0, (size_t)m * sizeof(uint32_t), stream);
@@ -278,16 +321,50 @@ hipError_t launch_bkmeans(const uint64_t* codes, uint32_t words, const uint32_t*
   return hipGetLastError();
 }
 
+size_t dac_top_scratch_bytes(uint32_t n, uint32_t m, uint32_t words, uint32_t T) {
+  if (!run_supported(m, words, T)) return 0;
+  return ((prep_bytes(m, words) + 255) & ~size_t(255)) + (size_t)n * T * sizeof(uint16_t);
+}
+
 hipError_t launch_dac(const uint64_t* codes, uint32_t n, uint32_t words, const uint64_t* centres,
                       uint32_t m, uint32_t T, uint32_t coarse_num, uint32_t K, uint32_t* top,
                       uint32_t* size, uint32_t* off, uint32_t* cursor, uint32_t* member,
-                      uint64_t* hcodes, uint32_t* out_idx, uint16_t* out_dist,
+                      uint64_t* hcodes, uint32_t* out_idx, uint16_t* out_dist, void* top_scratch,
                       hipStream_t stream) {
   if (words == 0 || words > kDMaxWords || m == 0 || T == 0 || T > 64 || K == 0 || K > 256)
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL(top_centres_kernel, dim3((n + 3) / 4), dim3(256), 0, stream, codes, n, words,
-                     centres, m, T, top);
-  hipError_t e = hipMemsetAsync(size, 0, (size_t)m * sizeof(uint32_t), stream);
+  hipError_t e = hipSuccess;
+  if (top_scratch != nullptr && run_supported(m, words, T)) {
+    // The exhaustive comparison of every row with the centres is a rectangular
+    // tile on the matrix cores: rows = the codes, columns = the centres, K = T,
+    // (distance, centre) order, no own-row exclusion.
+    char* frags = static_cast<char*>(top_scratch);
+    uint16_t* tdist =
+        reinterpret_cast<uint16_t*>(frags + ((prep_bytes(m, words) + 255) & ~size_t(255)));
+    e = launch_prep(centres, m, words, frags, stream);
+    if (e != hipSuccess) return e;
+    RunArgs a;
+    a.codes = codes;
+    a.frags = frags;
+    a.words = words;
+    a.bits = words * 64;
+    a.K = T;
+    a.idx_bits = run_idx_bits(words * 64);
+    a.row0 = 0;
+    a.nrows = n;
+    a.cb = 0;
+    a.ce = m;
+    a.fresh = 1;
+    a.out_idx = top;
+    a.out_dist = tdist;
+    a.rect = 1;
+    e = launch_mfma_run(a, stream);
+  } else {
+    hipLaunchKernelGGL(top_centres_kernel, dim3((n + 3) / 4), dim3(256), 0, stream, codes, n,
+                       words, centres, m, T, top);
+  }
+  if (e != hipSuccess) return e;
+  e = hipMemsetAsync(size, 0, (size_t)m * sizeof(uint32_t), stream);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(home_size_kernel, grid_of(n), dim3(256), 0, stream, top, n, T, size);
   hipLaunchKernelGGL(offsets_kernel, dim3(1), dim3(1), 0, stream, size, m, off, cursor);

@@ -48,14 +48,19 @@ hipError_t launch_propagate(const uint64_t* codes, uint32_t n, uint32_t words, u
 // [m][words][64], size [m]). launch_dac: the approximate graph (device
 // scratch: top [n][T], size [m], off [m + 1], cursor [m], member [n],
 // hcodes [n][words]). Row indices in sample / init must be < n.
+size_t bkmeans_tile_scratch_bytes(uint32_t ns, uint32_t m, uint32_t words);
 hipError_t launch_bkmeans(const uint64_t* codes, uint32_t words, const uint32_t* sample,
                           uint32_t ns, const uint32_t* init, uint32_t m, uint32_t iters,
                           uint64_t* centres, uint32_t* home, uint32_t* cnt, uint32_t* size,
-                          hipStream_t stream);
+                          void* tile_scratch, hipStream_t stream);
+// top_scratch (dac_top_scratch_bytes, 256-aligned) lets the nearest-centre
+// step run on the matrix cores; 0 bytes means the tile does not take the shape.
+size_t dac_top_scratch_bytes(uint32_t n, uint32_t m, uint32_t words, uint32_t T);
 hipError_t launch_dac(const uint64_t* codes, uint32_t n, uint32_t words, const uint64_t* centres,
                       uint32_t m, uint32_t T, uint32_t coarse_num, uint32_t K, uint32_t* top,
                       uint32_t* size, uint32_t* off, uint32_t* cursor, uint32_t* member,
-                      uint64_t* hcodes, uint32_t* out_idx, uint16_t* out_dist, hipStream_t stream);
+                      uint64_t* hcodes, uint32_t* out_idx, uint16_t* out_dist, void* top_scratch,
+                      hipStream_t stream);
 
 // Running-merge tile on the int8 matrix cores (tile_mfma.hip). One launch
 // merges columns [cb, ce) into the lists of rows [row0, row0 + nrows); the
@@ -70,6 +75,9 @@ struct RunArgs {
   int fresh;
   uint32_t* out_idx;
   uint16_t* out_dist;
+  // Rows and columns are different code sets (codes: the rows; frags: the
+  // columns), so no column is a row's own pair.
+  int rect = 0;
 };
 
 uint32_t run_idx_bits(uint32_t bits);

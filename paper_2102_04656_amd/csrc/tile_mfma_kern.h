@@ -148,6 +148,7 @@ struct TileJob {
   int fresh;
   uint32_t* out_idx;
   uint16_t* out_dist;
+  int rect;  // rows and columns are different code sets: no own-row exclusion
 };
 
 constexpr int kMaxWaves = 8;  // compute waves of a work-group, at most
@@ -239,6 +240,7 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
   const uint32_t row0 = job.row0, nrows = job.nrows, cb = job.cb, ce = job.ce;
   const uint32_t colbase = job.colbase;
   const int fresh = job.fresh;
+  const int rect = job.rect;
   uint32_t* __restrict__ out_idx = job.out_idx;
   uint16_t* __restrict__ out_dist = job.out_dist;
   uint32_t* lists = state;                // [NW][QW][K]
@@ -363,7 +365,7 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
   auto append = [&](const v4i (&acc)[QG], const int (&bb)[QG], const uint32_t cs) {
     const uint32_t c0 = cs + 4 * kq;
     const bool edge = cs < cb || cs + 16 > ce;   // group crosses the column range
-    const bool diag = cs < qhi && cs + 16 > qlo;  // group holds some of the wave's rows
+    const bool diag = !rect && cs < qhi && cs + 16 > qlo;  // group holds some of the wave's rows
 #pragma unroll
     for (int gq = 0; gq < QG; ++gq) {
       const int m4 = max(max(acc[gq][0], acc[gq][1]), max(acc[gq][2], acc[gq][3]));
@@ -376,7 +378,7 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const uint32_t col = c0 + r;
-          lim[r] = (col < cb || col >= ce || col == qrow[gq]) ? 0x7FFFFFFF : 0;
+          lim[r] = (col < cb || col >= ce || (!rect && col == qrow[gq])) ? 0x7FFFFFFF : 0;
         }
       }
       uint32_t pass[4];
@@ -623,6 +625,7 @@ __global__ __launch_bounds__(threads_of(W, NR), 1) void knn_mfma_batched_kernel(
     job.ce = b.hi;
     job.colbase = b.lo;
     job.fresh = 1;
+    job.rect = 0;
     job.out_idx = out_idx + (size_t)b.row0 * K;
     job.out_dist = out_dist + (size_t)b.row0 * K;
     tile_body<W, NR, QG, GPS, NST, use_producer(W, NR), waves_of_nr(NR)>(frags, codes, K, bits, IB,
@@ -665,6 +668,7 @@ inline hipError_t launch_run_w(const RunArgs& a, hipStream_t stream) {
   job.ce = a.ce;
   job.colbase = 0;
   job.fresh = a.fresh;
+  job.rect = a.rect;
   job.out_idx = a.out_idx;
   job.out_dist = a.out_dist;
   hipLaunchKernelGGL(kern, grid, dim3(threads_of(W, NR)), lds, stream,
