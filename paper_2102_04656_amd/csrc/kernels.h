@@ -76,7 +76,7 @@ struct RunArgs {
   uint32_t* out_idx;
   uint16_t* out_dist;
   // Rows and columns are different code sets (codes: the rows; frags: the
-  // columns), so no column is a row's own pair.
+  // columns), so no column is a row's own pair. K <= 64 only.
   int rect = 0;
 };
 

@@ -148,7 +148,6 @@ struct TileJob {
   int fresh;
   uint32_t* out_idx;
   uint16_t* out_dist;
-  int rect;  // rows and columns are different code sets: no own-row exclusion
 };
 
 constexpr int kMaxWaves = 8;  // compute waves of a work-group, at most
@@ -218,7 +217,9 @@ __device__ __forceinline__ void produce_stages(TileRing<SV4, NST>& ring, const v
 
 // The work of one work-group on one tile job; q0_wg = first job row of the
 // work-group (the job's rows are split over work-groups of NW QW rows).
-template <int W, int NR, int QG, int GPS, int NST, bool PROD, int NW>
+// RECT: rows and columns are different code sets (no column is a row's own
+// pair), for the rectangular searches of the divide-and-conquer.
+template <int W, int NR, int QG, int GPS, int NST, bool PROD, int NW, bool RECT = false>
 __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
                                           const uint64_t* __restrict__ codes, uint32_t K,
                                           uint32_t bits, uint32_t IB, const TileJob& job,
@@ -240,7 +241,7 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
   const uint32_t row0 = job.row0, nrows = job.nrows, cb = job.cb, ce = job.ce;
   const uint32_t colbase = job.colbase;
   const int fresh = job.fresh;
-  const int rect = job.rect;
+  constexpr bool rect = RECT;
   uint32_t* __restrict__ out_idx = job.out_idx;
   uint16_t* __restrict__ out_dist = job.out_dist;
   uint32_t* lists = state;                // [NW][QW][K]
@@ -588,15 +589,15 @@ constexpr int stages_of(int W, int NR) {
 
 // One (row block, column block) tile per launch; work-group g takes rows
 // [R g, R g + R) of the row block, R = NW QW.
-template <int W, int NR, int QG, int GPS, int NST>
+template <int W, int NR, int QG, int GPS, int NST, bool RECT = false>
 __global__ __launch_bounds__(threads_of(W, NR), 1) void knn_mfma_run_kernel(
     const v4i* __restrict__ frags, const uint64_t* __restrict__ codes, uint32_t K, uint32_t bits,
     uint32_t IB, TileJob job) {
   __shared__ TileRing<GPS * W * 64, NST> ring;
   extern __shared__ uint32_t state[];
   constexpr int NW = waves_of_nr(NR);
-  tile_body<W, NR, QG, GPS, NST, use_producer(W, NR), NW>(frags, codes, K, bits, IB, job,
-                                                          blockIdx.x * (NW * 16 * QG), ring, state);
+  tile_body<W, NR, QG, GPS, NST, use_producer(W, NR), NW, RECT>(
+      frags, codes, K, bits, IB, job, blockIdx.x * (NW * 16 * QG), ring, state);
 }
 
 // Many independent partitions in one persistent launch: every work-group
@@ -625,7 +626,6 @@ __global__ __launch_bounds__(threads_of(W, NR), 1) void knn_mfma_batched_kernel(
     job.ce = b.hi;
     job.colbase = b.lo;
     job.fresh = 1;
-    job.rect = 0;
     job.out_idx = out_idx + (size_t)b.row0 * K;
     job.out_dist = out_dist + (size_t)b.row0 * K;
     tile_body<W, NR, QG, GPS, NST, use_producer(W, NR), waves_of_nr(NR)>(frags, codes, K, bits, IB,
@@ -654,7 +654,14 @@ inline hipError_t launch_run_w(const RunArgs& a, hipStream_t stream) {
   constexpr int GPS = stage_groups(W, NR);
   constexpr int NST = stages_of(W, NR);
   static_assert(NST >= 2, "stage ring needs two slots");
+  // the rectangular variant exists for lists of up to 64 keys only
   auto kern = knn_mfma_run_kernel<W, NR, QG, GPS, NST>;
+  if (a.rect) {
+    if constexpr (NR == 1)
+      kern = knn_mfma_run_kernel<W, NR, QG, GPS, NST, true>;
+    else
+      return hipErrorInvalidValue;
+  }
   const size_t lds = run_state_bytes(a.K, QG);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -668,7 +675,6 @@ inline hipError_t launch_run_w(const RunArgs& a, hipStream_t stream) {
   job.ce = a.ce;
   job.colbase = 0;
   job.fresh = a.fresh;
-  job.rect = a.rect;
   job.out_idx = a.out_idx;
   job.out_dist = a.out_dist;
   hipLaunchKernelGGL(kern, grid, dim3(threads_of(W, NR)), lds, stream,
