@@ -24,6 +24,9 @@ Contents
   * ``bkmeans``, ``nearest_centres``, ``dac_graph`` -- the single-pass
                              divide-and-conquer (Sec. 3.2): binary centres,
                              budgeted multi-assignment, partition search.
+  * ``graph_search``      -- one query of the online search (Sec. 3.5):
+                             sampled entry, hill-climbing with a candidate
+                             pool, float32 re-rank of the pool.
 Floating-point parts (the binarisers, the float-kNN ground truth, the encoder
 network, its loss and optimiser) live in ``oracle.learned``.
 """
@@ -371,3 +374,78 @@ def dac_graph(codes: np.ndarray, centres: np.ndarray, T: int, coarse_num: int, K
         out_idx[r, : order.size] = c[order]
         out_dist[r, : order.size] = d[order]
     return out_idx, out_dist
+
+
+# --------------------------------------------------------------------------
+# Online search on the graph (Sec. 3.5): sampled entry points, hill-climbing
+# with a candidate pool, re-rank of the pool by real-valued features
+# --------------------------------------------------------------------------
+
+def l2_f32(a: np.ndarray, b: np.ndarray) -> np.float32:
+    """Squared L2 distance in float32, accumulated over the dimensions in
+    order: acc = acc + (a_i - b_i)^2, every operation rounded to float32
+    (no fused multiply-add)."""
+    acc = np.float32(0.0)
+    for ai, bi in zip(a.astype(np.float32), b.astype(np.float32)):
+        t = np.float32(ai - bi)
+        acc = np.float32(acc + np.float32(t * t))
+    return acc
+
+
+def graph_search(codes: np.ndarray, graph_idx: np.ndarray, feats: np.ndarray, q_code, q_feat,
+                 entries, P: int, N: int, exclude=None, max_expand: int = 1 << 20):
+    """One query of the online search (Sec. 3.5).
+
+    Entry point: the nearest of the sampled rows ``entries`` to the query
+    (Hamming; ties to the smaller index); only it starts the pool and counts
+    as visited (the other samples stay reachable through the graph).
+    Hill-climbing with a candidate pool of the P smallest (ham, idx) seen:
+    repeatedly expand the smallest pool member not yet expanded (every
+    neighbour in its graph row not visited before is measured, marked
+    visited and offered to the pool), until every pool member is expanded.
+    ``exclude`` (the query's own row) is never measured. Re-rank: all pool
+    members by ``l2_f32`` to the query's features, ties to the smaller
+    index; returns (idx [N], dist float32 [N]) padded with (0xFFFFFFFF,
+    inf), and the number of rows visited.
+    """
+    codes = np.ascontiguousarray(codes, dtype=np.uint64)
+    n = codes.shape[0]
+    q_code = np.asarray(q_code, dtype=np.uint64)
+
+    def ham(j):
+        return sum(bin(int(a) ^ int(b)).count("1") for a, b in zip(q_code, codes[j]))
+
+    visited = set() if exclude is None else {int(exclude)}
+    best = None
+    for e in [int(x) for x in entries]:
+        if e in visited or e >= n:
+            continue
+        k = (ham(e), e)
+        best = k if best is None or k < best else best
+    if best is not None:
+        visited.add(best[1])
+    out_idx = np.full(N, NO_IDX, dtype=np.uint32)
+    out_dist = np.full(N, np.inf, dtype=np.float32)
+    if best is None:
+        return out_idx, out_dist, len(visited)
+    pool = [best]            # sorted (ham, idx), at most P
+    expanded = set()
+    steps = 0
+    while steps < max_expand:
+        cand = [k for k in pool if k[1] not in expanded]
+        if not cand:
+            break
+        u = cand[0][1]
+        expanded.add(u)
+        steps += 1
+        for v in [int(x) for x in graph_idx[u]]:
+            if v == NO_IDX or v >= n or v in visited:
+                continue
+            visited.add(v)
+            pool.append((ham(v), v))
+        pool = sorted(pool)[:P]
+    rr = sorted((l2_f32(feats[j], q_feat), j) for _, j in pool)[:N]
+    for k, (d, j) in enumerate(rr):
+        out_idx[k] = j
+        out_dist[k] = d
+    return out_idx, out_dist, len(visited)
