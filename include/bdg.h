@@ -189,6 +189,34 @@ int bdg_build_knn_dac(const uint64_t *codes, uint32_t n, uint32_t bits, const ui
                       uint32_t m, uint32_t T, uint32_t coarse_num, uint32_t K, uint32_t *out_idx,
                       uint16_t *out_dist, void *stream);
 
+/*
+ * Online search on the graph (Sec. 3.5): for each query, the nearest of the
+ * S sampled rows `entries` (Hamming; ties to the smaller index) is the entry
+ * point; hill-climbing keeps a candidate pool of the P smallest
+ * (ham, index) seen and repeatedly expands the smallest pool member not yet
+ * expanded (every neighbour in its graph row not visited before is marked
+ * visited, measured and offered to the pool) until every pool member is
+ * expanded; the pool is then re-ranked by squared L2 of the real-valued
+ * features in float32 (each operation rounded, dimensions in order, ties to
+ * the smaller index) and the N best are returned.
+ *   codes [n][bits/64] uint64, graph [n][K] uint32 (absent: BDG_NO_IDX or
+ *   >= n), feats [n][d] float, q_codes [nq][bits/64], q_feats [nq][d],
+ *   q_exclude [nq] uint32 or NULL (a row each query must not return, e.g.
+ *   its own), entries [S] uint32: all device
+ *   out_idx [nq][N] uint32, out_dist [nq][N] float (padding BDG_NO_IDX,
+ *   +inf), out_visited [nq] uint32 or NULL (rows visited per query)
+ * 1 <= N <= P <= 256, n < 2^31. Visited bitmaps (n/8 bytes per query, in
+ * batches of at most 1 GiB) are allocated and freed on `stream`. Errors:
+ * BDG_EINVAL (bits, zero sizes, N > P, null pointer), BDG_EUNSUPPORTED
+ * (P > 256, K > BDG_MAX_K, bits > BDG_MAX_BITS, n >= 2^31), BDG_ENOMEM,
+ * BDG_EDEVICE.
+ */
+int bdg_graph_search(const uint64_t *codes, uint32_t n, uint32_t bits, const uint32_t *graph,
+                     uint32_t K, const float *feats, uint32_t d, const uint64_t *q_codes,
+                     const float *q_feats, const uint32_t *q_exclude, uint32_t nq,
+                     const uint32_t *entries, uint32_t S, uint32_t P, uint32_t N,
+                     uint32_t *out_idx, float *out_dist, uint32_t *out_visited, void *stream);
+
 /* ---------------------------------------------------- many partitions --- */
 
 /*

@@ -116,6 +116,8 @@ _SIGS = {
     "bdg_propagate": [_p, _u32, _u32, _u32, _p, _p, _p, _p],
     "bdg_bkmeans": [_p, _u32, _u32, _p, _u32, _p, _u32, _u32, _p, _p],
     "bdg_build_knn_dac": [_p, _u32, _u32, _p, _u32, _u32, _u32, _u32, _p, _p, _p],
+    "bdg_graph_search": [_p, _u32, _u32, _p, _u32, _p, _u32, _p, _p, _p, _u32, _p, _u32, _u32,
+                         _u32, _p, _p, _p, _p],
     "bdg_batch_plan_create": [_p, _u32, _u32, _u32, _p, _p],
     "bdg_batch_plan_destroy": [_p],
     "bdg_batch_plan_info": [_p, _p],
@@ -295,6 +297,26 @@ def build_knn_dac(codes, centres, K: int, T: int, coarse_num: int, bits: int | N
            torch.empty((n, K), dtype=torch.int16, device=codes.device))
     _check(lib().bdg_build_knn_dac(_ptr(codes), n, bits, _ptr(centres), centres.shape[0], T,
                                    coarse_num, K, _ptr(out[0]), _ptr(out[1]), _stream(stream)))
+    return out
+
+
+def graph_search(codes, graph, feats, q_codes, q_feats, entries, P: int, N: int,
+                 q_exclude=None, bits: int | None = None, stream=None):
+    """Online search (GPU tensors): returns (idx int32 [nq][N], dist float32
+    [nq][N], visited int32 [nq])."""
+    import torch
+    n, K = graph.shape
+    d = feats.shape[1]
+    nq = q_codes.shape[0]
+    bits = bits or codes.shape[1] * 64
+    dev = codes.device
+    out = (torch.empty((nq, N), dtype=torch.int32, device=dev),
+           torch.empty((nq, N), dtype=torch.float32, device=dev),
+           torch.empty((nq,), dtype=torch.int32, device=dev))
+    _check(lib().bdg_graph_search(
+        _ptr(codes), n, bits, _ptr(graph), K, _ptr(feats), d, _ptr(q_codes), _ptr(q_feats),
+        _ptr(q_exclude) if q_exclude is not None else None, nq, _ptr(entries), entries.shape[0],
+        P, N, _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _stream(stream)))
     return out
 
 

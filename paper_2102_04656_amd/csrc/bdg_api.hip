@@ -421,4 +421,43 @@ int bdg_build_knn_dac(const uint64_t* codes, uint32_t n, uint32_t bits, const ui
   return BDG_OK;
 }
 
+int bdg_graph_search(const uint64_t* codes, uint32_t n, uint32_t bits, const uint32_t* graph,
+                     uint32_t K, const float* feats, uint32_t d, const uint64_t* q_codes,
+                     const float* q_feats, const uint32_t* q_exclude, uint32_t nq,
+                     const uint32_t* entries, uint32_t S, uint32_t P, uint32_t N,
+                     uint32_t* out_idx, float* out_dist, uint32_t* out_visited, void* stream) {
+  g_last_error.clear();
+  if (bits == 0 || bits % 64 != 0)
+    return set_error(BDG_EINVAL, "bits must be a positive multiple of 64 (got %u)", bits);
+  if (bits > BDG_MAX_BITS) return set_error(BDG_EUNSUPPORTED, "bits > %u", BDG_MAX_BITS);
+  if (K == 0 || d == 0 || S == 0 || P == 0 || N == 0)
+    return set_error(BDG_EINVAL, "K, d, S, P and N must be >= 1");
+  if (N > P) return set_error(BDG_EINVAL, "N must be <= P");
+  if (P > 256 || K > BDG_MAX_K) return set_error(BDG_EUNSUPPORTED, "P > 256 or K > %u", BDG_MAX_K);
+  if (n == 0xFFFFFFFFu || n > 0x7FFFFFFFu) return set_error(BDG_EUNSUPPORTED, "n must be < 2^31");
+  if (nq == 0 || n == 0) return BDG_OK;
+  if (!codes || !graph || !feats || !q_codes || !q_feats || !entries || !out_idx || !out_dist)
+    return set_error(BDG_EINVAL, "null pointer");
+  const uint32_t words = bits / 64;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
+  // visited bitmaps for a batch of queries, at most about 1 GiB of scratch
+  const size_t per_q = bdg::search_map_words(n) * sizeof(uint32_t);
+  size_t batch = ((size_t)1 << 30) / per_q;
+  if (batch < 1) batch = 1;
+  if (batch > nq) batch = nq;
+  uint32_t* maps = nullptr;
+  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&maps), batch * per_q, st);
+  if (e != hipSuccess) return set_error(BDG_ENOMEM, "scratch: %s", hipGetErrorString(e));
+  for (uint32_t q0 = 0; q0 < nq && e == hipSuccess; q0 += (uint32_t)batch) {
+    const uint32_t nb = (uint32_t)((nq - q0) < batch ? (nq - q0) : batch);
+    e = bdg::launch_search(codes, n, words, graph, K, feats, d, q_codes, q_feats, q_exclude, q0, nb,
+                           entries, S, P, N, maps, out_idx, out_dist, out_visited, st);
+  }
+  hipError_t f = hipFreeAsync(maps, st);
+  if (e != hipSuccess) return device_error(e, "search launch");
+  if (f != hipSuccess) return device_error(f, "search scratch");
+  return BDG_OK;
+}
+
 }  // extern "C"

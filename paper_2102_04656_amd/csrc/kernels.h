@@ -62,6 +62,16 @@ hipError_t launch_dac(const uint64_t* codes, uint32_t n, uint32_t words, const u
                       uint64_t* hcodes, uint32_t* out_idx, uint16_t* out_dist, void* top_scratch,
                       hipStream_t stream);
 
+// Online search (search.hip): queries q0..q0+nq of the arrays, visited
+// bitmaps maps [nq][search_map_words(n)] (scratch, cleared here).
+size_t search_map_words(uint32_t n);
+hipError_t launch_search(const uint64_t* codes, uint32_t n, uint32_t words, const uint32_t* graph,
+                         uint32_t K, const float* feats, uint32_t d, const uint64_t* qcodes,
+                         const float* qfeats, const uint32_t* qexcl, uint32_t q0, uint32_t nq,
+                         const uint32_t* entries, uint32_t S, uint32_t P, uint32_t N,
+                         uint32_t* maps, uint32_t* out_idx, float* out_dist, uint32_t* out_vis,
+                         hipStream_t stream);
+
 // Running-merge tile on the int8 matrix cores (tile_mfma.hip). One launch
 // merges columns [cb, ce) into the lists of rows [row0, row0 + nrows); the
 // lists live in out_idx/out_dist (row r at (r - row0) * K), which hold the
