@@ -227,7 +227,8 @@ def recall_leg():
             "graph_ms_learned": res["graph_seconds_learned"] * 1e3,
             "graph_ms_srp": res["graph_seconds_srp"] * 1e3,
             "float_knn_ms": {"train_pairs": res["train_knn_seconds"] * 1e3,
-                             "eval_truth": res["exact_knn_seconds"] * 1e3}}
+                             "eval_truth": res["exact_knn_seconds"] * 1e3},
+            "search_recall_at_60": {"srp": res["search_srp"], "learned": res["search_learned"]}}
 
 
 def propagation_leg(codes, codes_dev, exact, bits, K, with_oracle, steps=3):

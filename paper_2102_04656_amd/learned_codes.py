@@ -172,7 +172,33 @@ class Workload:
         gi, _ = bdg.build_knn(codes, self.K_eval, row_block=131072, col_block=131072)
         torch.cuda.synchronize()
         t_graph = time.perf_counter() - t0
+        self.last = (codes, gi)
         return recall_at(gi[self.q], self.exact, self.K_eval), t_enc, t_graph
+
+    def search_eval(self, pools=(64, 128, 256), N=60, S=1024, seed=2105):
+        """Online search (Sec. 3.5) on the last graph: the 10k evaluation rows
+        as queries (their own rows excluded), S seeded entry samples, pool
+        sizes P; recall@N against exact float kNN and the time per query."""
+        import torch
+        codes, gi = self.last
+        n = codes.shape[0]
+        g = torch.Generator(device="cuda")
+        g.manual_seed(seed)
+        entries = torch.randperm(n, generator=g, device="cuda")[:S].to(torch.int32)
+        qi = self.q.to(torch.int32)
+        qc, qf = codes[self.q].contiguous(), self.X[self.q].contiguous()
+        out = []
+        for P in pools:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            idx, _, vis = bdg.graph_search(codes, gi, self.X, qc, qf, entries, P, N, q_exclude=qi)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            out.append(dict(pool=P, recall=recall_at(idx, self.exact, N), ms=ms,
+                            us_per_query=ms * 1e3 / qi.numel(),
+                            rows_visited=float(vis.float().mean().item()) + S))
+        return out
 
     def evaluate_srp(self):
         return self.evaluate(lambda: bdg.encode_srp(self.X, self.P))
@@ -193,6 +219,8 @@ def experiment(steps=20000, T=1024, lr=3e-4, h=1024, loss_opts=None, sampler=Non
     r, te, tg = wl.evaluate_srp()
     res.update(recall_srp=r, encode_seconds_srp=te, graph_seconds_srp=tg)
     log(f"[g2] srp: recall@{wl.K_eval} {r:.4f} (encode {te:.3f}s, graph {tg:.3f}s)")
+    res["search_srp"] = wl.search_eval()
+    log(f"[g2] srp search: {res['search_srp']}")
     curve = []
 
     def cb(step, net):
@@ -208,6 +236,8 @@ def experiment(steps=20000, T=1024, lr=3e-4, h=1024, loss_opts=None, sampler=Non
     res.update(recall_learned=r, encode_seconds_learned=te, graph_seconds_learned=tg,
                train_seconds=tr["seconds"], loss_history=tr["history"], recall_curve=curve)
     log(f"[g2] learned: recall@{wl.K_eval} {r:.4f} (encode {te:.3f}s, graph {tg:.3f}s)")
+    res["search_learned"] = wl.search_eval()
+    log(f"[g2] learned search: {res['search_learned']}")
     return res, net
 
 
