@@ -205,10 +205,10 @@ int bdg_build_knn_dac(const uint64_t *codes, uint32_t n, uint32_t bits, const ui
  *   its own), entries [S] uint32: all device
  *   out_idx [nq][N] uint32, out_dist [nq][N] float (padding BDG_NO_IDX,
  *   +inf), out_visited [nq] uint32 or NULL (rows visited per query)
- * 1 <= N <= P <= 256, n < 2^31. Visited bitmaps (n/8 bytes per query, in
+ * 1 <= N <= P <= 1024, n < 2^31. Visited bitmaps (n/8 bytes per query, in
  * batches of at most 1 GiB) are allocated and freed on `stream`. Errors:
  * BDG_EINVAL (bits, zero sizes, N > P, null pointer), BDG_EUNSUPPORTED
- * (P > 256, K > BDG_MAX_K, bits > BDG_MAX_BITS, n >= 2^31), BDG_ENOMEM,
+ * (P > 1024, K > BDG_MAX_K, bits > BDG_MAX_BITS, n >= 2^31), BDG_ENOMEM,
  * BDG_EDEVICE.
  */
 int bdg_graph_search(const uint64_t *codes, uint32_t n, uint32_t bits, const uint32_t *graph,

@@ -433,7 +433,7 @@ int bdg_graph_search(const uint64_t* codes, uint32_t n, uint32_t bits, const uin
   if (K == 0 || d == 0 || S == 0 || P == 0 || N == 0)
     return set_error(BDG_EINVAL, "K, d, S, P and N must be >= 1");
   if (N > P) return set_error(BDG_EINVAL, "N must be <= P");
-  if (P > 256 || K > BDG_MAX_K) return set_error(BDG_EUNSUPPORTED, "P > 256 or K > %u", BDG_MAX_K);
+  if (P > 1024 || K > BDG_MAX_K) return set_error(BDG_EUNSUPPORTED, "P > 1024 or K > %u", BDG_MAX_K);
   if (n == 0xFFFFFFFFu || n > 0x7FFFFFFFu) return set_error(BDG_EUNSUPPORTED, "n must be < 2^31");
   if (nq == 0 || n == 0) return BDG_OK;
   if (!codes || !graph || !feats || !q_codes || !q_feats || !entries || !out_idx || !out_dist)

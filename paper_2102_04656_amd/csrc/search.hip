@@ -197,7 +197,7 @@ hipError_t launch_search(const uint64_t* codes, uint32_t n, uint32_t words, cons
                          uint32_t* maps, uint32_t* out_idx, float* out_dist, uint32_t* out_vis,
                          hipStream_t stream) {
   if (nq == 0) return hipSuccess;
-  if (words == 0 || words > kSMaxWords || P == 0 || P > 256 || N == 0 || N > P || K == 0)
+  if (words == 0 || words > kSMaxWords || P == 0 || P > 1024 || N == 0 || N > P || K == 0)
     return hipErrorInvalidValue;
   const uint32_t mapw = (uint32_t)search_map_words(n);
   hipError_t e = hipMemsetAsync(maps, 0, (size_t)nq * mapw * sizeof(uint32_t), stream);
@@ -211,10 +211,18 @@ hipError_t launch_search(const uint64_t* codes, uint32_t n, uint32_t words, cons
     hipLaunchKernelGGL(search_kernel<2>, grid, dim3(256), 0, stream, codes, n, words, graph, K, feats,
                        d, qcodes, qfeats, qexcl, q0, nq, entries, S, P, N, maps, mapw, out_idx,
                        out_dist, out_vis);
-  else
+  else if (P <= 256)
     hipLaunchKernelGGL(search_kernel<4>, grid, dim3(256), 0, stream, codes, n, words, graph, K, feats,
                        d, qcodes, qfeats, qexcl, q0, nq, entries, S, P, N, maps, mapw, out_idx,
                        out_dist, out_vis);
+  else if (P <= 512)
+    hipLaunchKernelGGL(search_kernel<8>, grid, dim3(256), 0, stream, codes, n, words, graph, K, feats,
+                       d, qcodes, qfeats, qexcl, q0, nq, entries, S, P, N, maps, mapw, out_idx,
+                       out_dist, out_vis);
+  else
+    hipLaunchKernelGGL(search_kernel<16>, grid, dim3(256), 0, stream, codes, n, words, graph, K,
+                       feats, d, qcodes, qfeats, qexcl, q0, nq, entries, S, P, N, maps, mapw,
+                       out_idx, out_dist, out_vis);
   return hipGetLastError();
 }
 

@@ -175,7 +175,7 @@ class Workload:
         self.last = (codes, gi)
         return recall_at(gi[self.q], self.exact, self.K_eval), t_enc, t_graph
 
-    def search_eval(self, pools=(64, 128, 256), N=60, S=1024, seed=2105):
+    def search_eval(self, pools=(64, 256, 1024), N=60, S=1024, seed=2105):
         """Online search (Sec. 3.5) on the last graph: the 10k evaluation rows
         as queries (their own rows excluded), S seeded entry samples, pool
         sizes P; recall@N against exact float kNN and the time per query."""

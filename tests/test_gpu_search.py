@@ -44,6 +44,8 @@ def run_gpu(codes, gi, feats, qc, qf, excl, entries, P, N):
     (2000, 32, 128, 16, 64, 20, 52, False),
     (1500, 48, 256, 24, 100, 60, 53, True),   # two rows of pool keys, holed graph
     (1200, 16, 64, 12, 256, 60, 54, False),   # four rows of pool keys
+    (2500, 24, 128, 16, 512, 60, 56, False),  # eight rows
+    (3000, 24, 128, 20, 1000, 100, 57, True), # sixteen rows, ragged
 ])
 def test_search_matches_oracle(n, d, bits, K, P, N, seed, holes):
     print(f"[search] n={n} d={d} bits={bits} K={K} P={P} N={N}", flush=True)
