@@ -46,7 +46,7 @@ def log(*a):
 # Sources that define each timed kernel: a recorded HBM-traffic figure is
 # reported only while they are unchanged since the counters were taken.
 KERNEL_SOURCES = {
-    "knn_mfma_run_kernel": ["tile_mfma_kern.h", "wave_topk.h", "tile_mfma.hip", "kernels.h"],
+    "knn_mfma_sweep_kernel": ["tile_mfma_kern.h", "wave_topk.h", "tile_mfma.hip", "kernels.h"],
     "knn_mfma_batched_kernel": ["tile_mfma_kern.h", "wave_topk.h", "tile_mfma.hip", "kernels.h"],
     "knn_popc_kernel": ["knn_tiles.hip", "wave_topk.h", "kernels.h"],
 }
@@ -126,16 +126,15 @@ def run_path(codes_dev, n, bits, K, path, row_block, col_block, steps, warmup):
     """Time `steps` full builds; returns (ms/step, tile kernel stats, outputs).
 
     The distance-tile launches of one build are, in order: one per row block
-    (popc: all columns, per-block lists merged afterwards) or one per (row
-    block, column block) pair (mfma: lists carried across column blocks)."""
+    (popc: all columns, per-block lists merged afterwards) or a single
+    persistent launch (mfma: (row tile, column block) items, lists carried
+    across column blocks)."""
     import torch
     from paper_2102_04656_amd import bdg
 
     nrb = (n + row_block - 1) // row_block
-    ncb = (n + col_block - 1) // col_block
     if path == bdg.PATH_MFMA:
-        shapes = [(min(row_block, n - r * row_block), min(col_block, n - c * col_block))
-                  for r in range(nrb) for c in range(ncb)]
+        shapes = [(n, n)]  # one persistent launch over all (row tile, column block) items
     else:
         shapes = [(min(row_block, n - r * row_block), n) for r in range(nrb)]
     nl = len(shapes)
@@ -516,7 +515,7 @@ def main():
     else:
         ops_pair, peak, bound = 2 * bits // 32, PEAK_VALU_TOPS, "alu"
     achieved = kern["pairs_per_launch"] * ops_pair / (kern["avg_ms"] * 1e-3) / 1e12
-    kname = "knn_mfma_run_kernel" if main_path == "mfma" else "knn_popc_kernel"
+    kname = "knn_mfma_sweep_kernel" if main_path == "mfma" else "knn_popc_kernel"
     result = {
         "metric": METRIC,
         "value": pairs / (ms * 1e-3),

@@ -79,10 +79,12 @@ typedef struct bdg_knn_opts {
     uint32_t tile_variant;   /* batched plans: work order (BDG_ORDER_*); else 0 */
     uint32_t n_tile_events;  /* length of tile_events (0 = no timing) */
     void **tile_events;      /* optional caller-created hipEvent_t handles: for
-                                the i-th tile launch of the call (one per row
-                                block, in order), events [2i] and [2i + 1] are
-                                recorded on the stream just before and just
-                                after it, while 2i + 1 < n_tile_events */
+                                the i-th tile launch of the call (vector-ALU
+                                path: one per row block, in order; matrix-core
+                                path: one launch for the whole call), events
+                                [2i] and [2i + 1] are recorded on the stream
+                                just before and just after it, while
+                                2i + 1 < n_tile_events */
     uint32_t reserved[4];
 } bdg_knn_opts;
 
@@ -104,7 +106,12 @@ int bdg_build_knn(const uint64_t *codes, uint32_t n, uint32_t bits, uint32_t K,
 /* As bdg_build_knn, enqueued on `stream` with options (opts may be NULL). The
  * graph is built blockwise: row blocks x column blocks; each column block
  * yields per-row top-K lists that are merged (as bdg_merge_lists) into the
- * output. With opts->workspace set, the call allocates nothing. */
+ * output. On the matrix-core path the blocks are the items of one persistent
+ * launch (tiles of rows x column blocks, a tile's blocks merged in column
+ * order); its workspace ends with control words (a claim counter, a stall
+ * flag that is never set in a correct run, and one progress word per tile).
+ * With opts->workspace set, the call allocates nothing. Calls on one
+ * workspace must not overlap. */
 int bdg_build_knn_ex(const uint64_t *codes, uint32_t n, uint32_t bits, uint32_t K,
                      uint32_t *out_idx, uint16_t *out_dist, const bdg_knn_opts *opts,
                      void *stream);

@@ -56,8 +56,9 @@ struct Plan {
   uint32_t row_block, col_block, nrb, ncb;
   int path;
   bool running;     // lists carried across column blocks in the output rows
-  size_t ws_bytes;  // operand fragments (running) or partial lists of one row block
-  size_t ws_idx_off, ws_dist_off;
+  size_t ws_bytes;  // operand fragments + sweep control words (running), or
+                    // partial lists of one row block
+  size_t ws_idx_off, ws_dist_off, ws_ctl_off;
 };
 
 int path_auto(uint32_t n, uint32_t words, uint32_t K) {
@@ -108,8 +109,10 @@ int make_plan(uint32_t n, uint32_t bits, uint32_t K, const bdg_knn_opts* opts, P
   if (p->ncb > 65535)
     return set_error(BDG_EUNSUPPORTED, "more than 65535 column blocks (col_block %u)", cb);
   p->running = path == BDG_PATH_MFMA;
+  p->ws_ctl_off = 0;
   if (p->running) {
-    p->ws_bytes = n ? align256(bdg::prep_bytes(n, p->words)) : 0;
+    p->ws_ctl_off = n ? align256(bdg::prep_bytes(n, p->words)) : 0;
+    p->ws_bytes = n ? p->ws_ctl_off + align256(bdg::sweep_ctl_words(n, K) * 4) : 0;
     p->ws_idx_off = p->ws_dist_off = 0;
   } else if (p->ncb > 1) {
     const size_t entries = (size_t)p->ncb * rb * K;
@@ -205,36 +208,36 @@ int bdg_build_knn_ex(const uint64_t* codes, uint32_t n, uint32_t bits, uint32_t 
 
   int result = BDG_OK;
   if (p.running) {
-    // Operand fragments of all codes, then row block x column block tiles,
-    // each merging its columns into the rows' running lists.
+    // Operand fragments of all codes, then the rows of the selected row blocks
+    // against every column block in one persistent launch, each (row tile,
+    // column block) item merging its columns into the rows' running lists.
     hipError_t e = bdg::launch_prep(codes, n, p.words, ws, stream);
-    uint32_t launch = 0;
-    for (uint32_t rb = first; rb < stop && e == hipSuccess; ++rb) {
-      const uint32_t r0 = rb * p.row_block;
-      const uint32_t nr = (n - r0 < p.row_block) ? n - r0 : p.row_block;
-      for (uint32_t c = 0; c < p.ncb && e == hipSuccess; ++c, ++launch) {
-        bdg::RunArgs a;
-        a.codes = codes;
-        a.frags = ws;
-        a.words = p.words;
-        a.bits = bits;
-        a.K = K;
-        a.idx_bits = bdg::run_idx_bits(bits);
-        a.row0 = r0;
-        a.nrows = nr;
-        a.cb = c * p.col_block;
-        a.ce = (n - a.cb < p.col_block) ? n : a.cb + p.col_block;
-        a.fresh = c == 0;
-        a.out_idx = out_idx + (size_t)r0 * K;
-        a.out_dist = out_dist + (size_t)r0 * K;
-        const bool timed = opts && opts->tile_events && 2 * launch + 1 < opts->n_tile_events;
-        if (timed)
-          e = hipEventRecord(reinterpret_cast<hipEvent_t>(opts->tile_events[2 * launch]), stream);
-        if (e == hipSuccess) e = bdg::launch_mfma_run(a, stream);
-        if (e == hipSuccess && timed)
-          e = hipEventRecord(reinterpret_cast<hipEvent_t>(opts->tile_events[2 * launch + 1]),
-                             stream);
-      }
+    int dev = 0, cus = 0;
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) {
+      const uint32_t r0 = first * p.row_block;
+      const uint64_t r1 = (uint64_t)stop * p.row_block;
+      bdg::SweepArgs a;
+      a.codes = codes;
+      a.frags = ws;
+      a.words = p.words;
+      a.bits = bits;
+      a.K = K;
+      a.idx_bits = bdg::run_idx_bits(bits);
+      a.row0 = r0;
+      a.nrows = (r1 < n ? (uint32_t)r1 : n) - r0;
+      a.ncols = n;
+      a.col_block = p.col_block;
+      a.ctl = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + p.ws_ctl_off);
+      a.grid = (uint32_t)(cus > 0 ? cus : 1);
+      a.out_idx = out_idx + (size_t)r0 * K;
+      a.out_dist = out_dist + (size_t)r0 * K;
+      const bool timed = opts && opts->tile_events && opts->n_tile_events >= 2;
+      if (timed) e = hipEventRecord(reinterpret_cast<hipEvent_t>(opts->tile_events[0]), stream);
+      if (e == hipSuccess) e = bdg::launch_mfma_sweep(a, stream);
+      if (e == hipSuccess && timed)
+        e = hipEventRecord(reinterpret_cast<hipEvent_t>(opts->tile_events[1]), stream);
     }
     if (e != hipSuccess) result = device_error(e, "tile launch");
   }

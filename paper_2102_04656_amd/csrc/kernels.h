@@ -118,4 +118,25 @@ struct BatchArgs {
 };
 hipError_t launch_mfma_batched(const BatchArgs& a, hipStream_t stream);
 
+// A whole build as one persistent launch: rows [row0, row0 + nrows) against
+// columns [0, ncols), as work items (tile of run_rows_per_wg(K) rows, column
+// block of col_block columns) taken column block by column block; an item
+// merges its columns into the tile's lists in out_idx/out_dist (row r at
+// (r - row0) * K) after the item of the previous column block has. ctl:
+// sweep_ctl_words(nrows, K) device words (claim counter, stall flag, one
+// progress word per tile), reset by the launch itself.
+struct SweepArgs {
+  const uint64_t* codes;
+  const void* frags;
+  uint32_t words, bits, K, idx_bits;
+  uint32_t row0, nrows, ncols, col_block;
+  uint32_t* ctl;
+  uint32_t grid;  // persistent work-groups
+  uint32_t* out_idx;
+  uint16_t* out_dist;
+};
+constexpr uint32_t kSweepStallWord = 1;  // ctl[1] != 0: a dependency wait ran out
+size_t sweep_ctl_words(uint32_t nrows, uint32_t K);
+hipError_t launch_mfma_sweep(const SweepArgs& a, hipStream_t stream);
+
 }  // namespace bdg

@@ -120,6 +120,35 @@ hipError_t launch_mfma_batched(const BatchArgs& a, hipStream_t stream) {
   }
 }
 
+size_t sweep_ctl_words(uint32_t nrows, uint32_t K) {
+  const uint32_t rt = run_rows_per_wg(K);
+  return 2 + ((size_t)nrows + rt - 1) / rt;
+}
+
+hipError_t launch_mfma_sweep(const SweepArgs& a, hipStream_t stream) {
+  if (a.nrows == 0 || a.ncols == 0) return hipSuccess;
+  if (a.col_block == 0 || a.grid == 0) return hipErrorInvalidValue;
+  switch (a.words) {
+    case 1: return mfma::launch_sweep_words<1>(a, stream);
+    case 2: return mfma::launch_sweep_words<2>(a, stream);
+    case 3: return mfma::launch_sweep_words<3>(a, stream);
+    case 4: return mfma::launch_sweep_words<4>(a, stream);
+    case 5: return mfma::launch_sweep_words<5>(a, stream);
+    case 6: return mfma::launch_sweep_words<6>(a, stream);
+    case 7: return mfma::launch_sweep_words<7>(a, stream);
+    case 8: return mfma::launch_sweep_words<8>(a, stream);
+    case 9: return mfma::launch_sweep_words<9>(a, stream);
+    case 10: return mfma::launch_sweep_words<10>(a, stream);
+    case 11: return mfma::launch_sweep_words<11>(a, stream);
+    case 12: return mfma::launch_sweep_words<12>(a, stream);
+    case 13: return mfma::launch_sweep_words<13>(a, stream);
+    case 14: return mfma::launch_sweep_words<14>(a, stream);
+    case 15: return mfma::launch_sweep_words<15>(a, stream);
+    case 16: return mfma::launch_sweep_words<16>(a, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_mfma_run(const RunArgs& a, hipStream_t stream) {
   if (a.nrows == 0 || a.ce <= a.cb) return hipSuccess;
   switch (a.words) {

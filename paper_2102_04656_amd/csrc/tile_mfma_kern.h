@@ -633,8 +633,79 @@ __global__ __launch_bounds__(threads_of(W, NR), 1) void knn_mfma_batched_kernel(
   }
 }
 
+// Bound on the polls of one dependency wait (each polls, then sleeps about
+// 1,000 cycles): seconds, far beyond any item. The wait order makes the bound
+// unreachable; it only guarantees that every wave exits.
+constexpr uint32_t kSweepSpinLimit = 1u << 23;
+
+// A whole build in one persistent launch (SweepArgs): every work-group takes
+// items (row tile t, column block c) from a shared counter in the order
+// c * ntiles + t, so that all work-groups stream the same column block at
+// once (it stays in L2) and the launch ends on a tail of at most one item per
+// work-group, where separate launches per block would each leave CUs idle in
+// their last round. Item (t, c > 0) merges into the lists item (t, c - 1)
+// wrote: it waits for progress[t] = c. That item was claimed earlier, by a
+// work-group already running, and its own wait is on a still earlier item,
+// down to a first-block item that waits for nothing, so every wait ends.
+template <int W, int NR, int QG, int GPS, int NST>
+__global__ __launch_bounds__(threads_of(W, NR), 1) void knn_mfma_sweep_kernel(
+    const v4i* __restrict__ frags, const uint64_t* __restrict__ codes, uint32_t K, uint32_t bits,
+    uint32_t IB, uint32_t row0, uint32_t nrows, uint32_t ncols, uint32_t col_block,
+    uint32_t ntiles, uint32_t nitems, uint32_t* ctl, uint32_t* __restrict__ out_idx,
+    uint16_t* __restrict__ out_dist) {
+  __shared__ TileRing<GPS * W * 64, NST> ring;
+  __shared__ uint32_t cur;
+  extern __shared__ uint32_t state[];
+  constexpr uint32_t RT = waves_of_nr(NR) * 16 * QG;  // rows per tile
+  uint32_t* progress = ctl + 2;
+  for (;;) {
+    __syncthreads();  // every wave is done with the previous item
+    if (threadIdx.x == 0) cur = atomicAdd(ctl, 1u);
+    __syncthreads();
+    const uint32_t it = cur;
+    if (it >= nitems) break;  // work-group-uniform: every wave leaves
+    const uint32_t c = it / ntiles, t = it - c * ntiles;
+    if (c > 0) {
+      if (threadIdx.x == 0) {
+        for (uint32_t spins = 0; __hip_atomic_load(&progress[t], __ATOMIC_ACQUIRE,
+                                                   __HIP_MEMORY_SCOPE_AGENT) < c;) {
+          if (++spins == kSweepSpinLimit) {
+            __hip_atomic_store(&ctl[kSweepStallWord], 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(16);
+        }
+      }
+      __syncthreads();
+      // the lists written by the previous item (on any XCD) are seen
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    TileJob job;
+    job.row0 = row0 + t * RT;
+    job.nrows = nrows - t * RT < RT ? nrows - t * RT : RT;
+    job.cb = c * col_block;
+    job.ce = ncols - job.cb < col_block ? ncols : job.cb + col_block;
+    job.colbase = 0;
+    job.fresh = c == 0;
+    job.out_idx = out_idx + (size_t)t * RT * K;
+    job.out_dist = out_dist + (size_t)t * RT * K;
+    tile_body<W, NR, QG, GPS, NST, use_producer(W, NR), waves_of_nr(NR)>(frags, codes, K, bits, IB,
+                                                                         job, 0, ring, state);
+    // the tile's lists are in the output rows: publish them
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0)
+      __hip_atomic_store(&progress[t], c + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 namespace {
 __global__ void zero_counter_kernel(uint32_t* counter) { *counter = 0; }
+__global__ void zero_words_kernel(uint32_t* w, uint32_t count) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) w[i] = 0;
+}
 }  // namespace
 
 inline int nr_of(uint32_t K) { return K <= 64 ? 1 : (K <= 128 ? 2 : 4); }
@@ -700,6 +771,42 @@ inline hipError_t launch_batched_w(const BatchArgs& a, hipStream_t stream) {
   return hipGetLastError();
 }
 
+template <int W, int NR>
+inline hipError_t launch_sweep_w(const SweepArgs& a, hipStream_t stream) {
+  constexpr int QG = qgroups_of_nr(NR);
+  constexpr int GPS = stage_groups(W, NR);
+  constexpr int NST = stages_of(W, NR);
+  static_assert(NST >= 2, "stage ring needs two slots");
+  auto kern = knn_mfma_sweep_kernel<W, NR, QG, GPS, NST>;
+  const size_t lds = run_state_bytes(a.K, QG);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const uint32_t rt = waves_of_nr(NR) * 16 * QG;
+  const uint32_t ntiles = (a.nrows + rt - 1) / rt;
+  const uint32_t ncb = (a.ncols + a.col_block - 1) / a.col_block;
+  if ((uint64_t)ntiles * ncb > 0xFFFFFFFFull) return hipErrorInvalidValue;
+  const uint32_t nitems = ntiles * ncb;
+  const uint32_t words = ntiles + 2;
+  hipLaunchKernelGGL(zero_words_kernel, dim3((words + 255) / 256), dim3(256), 0, stream, a.ctl,
+                     words);
+  const uint32_t grid = a.grid < nitems ? a.grid : nitems;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(threads_of(W, NR)), lds, stream,
+                     reinterpret_cast<const v4i*>(a.frags), a.codes, a.K, a.bits, a.idx_bits,
+                     a.row0, a.nrows, a.ncols, a.col_block, ntiles, nitems, a.ctl, a.out_idx,
+                     a.out_dist);
+  return hipGetLastError();
+}
+
+template <int W>
+inline hipError_t launch_sweep_nr(const SweepArgs& a, hipStream_t stream) {
+  switch (nr_of(a.K)) {
+    case 1: return launch_sweep_w<W, 1>(a, stream);
+    case 2: return launch_sweep_w<W, 2>(a, stream);
+    default: return launch_sweep_w<W, 4>(a, stream);
+  }
+}
+
 template <int W>
 inline hipError_t launch_batched_nr(const BatchArgs& a, hipStream_t stream) {
   switch (nr_of(a.K)) {
@@ -724,6 +831,8 @@ template <int W>
 hipError_t launch_run_words(const RunArgs& a, hipStream_t stream);
 template <int W>
 hipError_t launch_batched_words(const BatchArgs& a, hipStream_t stream);
+template <int W>
+hipError_t launch_sweep_words(const SweepArgs& a, hipStream_t stream);
 
 }  // namespace mfma
 }  // namespace bdg

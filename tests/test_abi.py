@@ -86,11 +86,17 @@ def test_workspace_size():
     ent = 4 * 300 * 8
     assert ws == ((ent * 4 + 255) // 256) * 256 + ((ent * 2 + 255) // 256) * 256
     # matrix-core path: the +-1 operand fragments of all codes (bits bytes per row,
-    # rows rounded up to 16 plus 256 rows of slack), whatever the blocking
+    # rows rounded up to 16 plus 256 rows of slack), whatever the blocking, then
+    # the sweep's control words (2 + one per tile of 256 rows for K <= 64),
+    # each part aligned to 256 bytes
     for kw in (dict(), dict(col_block=250, row_block=300)):
         o = bdg.make_opts(path=bdg.PATH_MFMA, **kw)
         ws = bdg.bdg_build_knn_workspace_size(1000, 256, 8, o)
-        assert ws == (((1000 + 15) // 16 * 16 + 256) * 256 + 255) // 256 * 256
+        assert ws == (((1000 + 15) // 16 * 16 + 256) * 256 + 255) // 256 * 256 + 256
+    o = bdg.make_opts(path=bdg.PATH_MFMA)
+    n = 300_000  # 1,172 tiles of 256 rows: 1,174 control words
+    ws = bdg.bdg_build_knn_workspace_size(n, 128, 64, o)
+    assert ws == (((n + 15) // 16 * 16 + 256) * 128 + 255) // 256 * 256 + (1174 * 4 + 255) // 256 * 256
 
 
 def test_batched_plan_rejects_bad_arguments():

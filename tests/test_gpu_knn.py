@@ -229,6 +229,40 @@ def test_caller_workspace_and_alloc_failure():
     assert (idx.cpu().numpy() == 5).all()
 
 
+@pytest.mark.parametrize("n,bits,K,col_block", [
+    (1500, 256, 24, 37),    # 6 tiles x 41 column blocks: chains of 41 dependent items
+    (2000, 512, 100, 300),  # tiles of 192 rows, lists of 128 keys
+    (700, 64, 8, 5000),     # one column block: no item waits
+])
+def test_sweep_control_words(n, bits, K, col_block):
+    # The matrix-core build is one persistent launch over (row tile, column
+    # block) items. Besides the graph, its control words at the end of the
+    # workspace show that every item ran once and no dependency wait ran out:
+    # claim counter = items + work-groups (each work-group's last claim finds
+    # the list empty), stall flag 0, every tile's progress = column blocks.
+    import torch
+    codes = datagen.clustered_codes(n, bits, 12, 0.2, seed=n + bits + K)
+    want = oracle.knn_rows(codes, K)
+    o = bdg.make_opts(path=MFMA, col_block=col_block)
+    need = bdg.bdg_build_knn_workspace_size(n, bits, K, o)
+    ws = torch.zeros(need, dtype=torch.uint8, device="cuda")
+    o.workspace, o.workspace_bytes = ws.data_ptr(), need
+    idx = torch.empty((n, K), dtype=torch.int32, device="cuda")
+    dist = torch.empty((n, K), dtype=torch.int16, device="cuda")
+    assert bdg.bdg_build_knn_ex(dev(codes), n, bits, K, idx, dist, o, None) == 0
+    torch.cuda.synchronize()
+    assert_same(bdg.to_numpy_graph(idx, dist), want, f"sweep n={n} col_block={col_block}")
+    rt = 256 if K <= 64 else 192
+    ntiles = -(-n // rt)
+    ncb = -(-n // col_block)
+    off = ((((n + 15) // 16 * 16 + 256) * bits) + 255) // 256 * 256
+    ctl = ws[off:off + 4 * (ntiles + 2)].cpu().numpy().view(np.uint32)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    assert ctl[0] == ntiles * ncb + min(cus, ntiles * ncb)
+    assert ctl[1] == 0
+    assert (ctl[2:] == ncb).all()
+
+
 def test_sync_entry_point():
     import torch
     codes = datagen.clustered_codes(900, 192, 9, 0.2, seed=47)
