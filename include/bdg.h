@@ -69,8 +69,9 @@ typedef struct bdg_knn_opts {
     uint32_t struct_size;
     int32_t path;            /* bdg_path; default AUTO */
     uint32_t row_block;      /* rows per row block (default 131072) */
-    uint32_t col_block;      /* columns per column block (default 131072,
-                                at most 2097152) */
+    uint32_t col_block;      /* columns per column block (default 262144 on
+                                the matrix-core path, 131072 on the vector-ALU
+                                path; at most 2097152) */
     void *workspace;         /* optional device scratch; if NULL the library
                                 allocates stream-ordered and frees before return */
     size_t workspace_bytes;  /* size of `workspace` */

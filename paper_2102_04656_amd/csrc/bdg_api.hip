@@ -41,6 +41,10 @@ int device_error(hipError_t e, const char* what) {
 }
 
 constexpr uint32_t kDefaultBlock = 131072;
+// Matrix-core path: the column-block width is the width of one work item of
+// the persistent launch; wider items spend less on list loads and stage-ring
+// fills per pair, and the launch still ends on a short tail.
+constexpr uint32_t kDefaultMfmaColBlock = 262144;
 constexpr uint32_t kMaxColBlock = 1u << 21;  // column index field of a tile key
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -93,8 +97,10 @@ int make_plan(uint32_t n, uint32_t bits, uint32_t K, const bdg_knn_opts* opts, P
     return set_error(BDG_EUNSUPPORTED, "path %d does not support n=%u bits=%u K=%u", path, n,
                      bits, K);
   p->path = path;
-  uint32_t cb = (opts && opts->col_block) ? opts->col_block
-                                          : (tuned_cb ? tuned_cb : kDefaultBlock);
+  uint32_t cb = (opts && opts->col_block)
+                    ? opts->col_block
+                    : (tuned_cb ? tuned_cb
+                                : (path == BDG_PATH_MFMA ? kDefaultMfmaColBlock : kDefaultBlock));
   uint32_t rb = (opts && opts->row_block) ? opts->row_block : kDefaultBlock;
   if (cb > kMaxColBlock)
     return set_error(BDG_EUNSUPPORTED, "col_block > %u", kMaxColBlock);

@@ -151,11 +151,11 @@ def gaussian_projection(d: int = 512, bits: int = 256, seed: int = 6) -> np.ndar
 WORKLOADS = {
     "clustered-20k-128b-k32": dict(n=20_000, bits=128, n_centres=100, p=0.15, seed=1, K=32),
     "clustered-1m-256b-k64": dict(n=1_000_000, bits=256, n_centres=1000, p=0.2, seed=2, K=64,
-                                  row_block=131072, col_block=131072),
+                                  row_block=131072, col_block=262144),
     "sharded-512x-256b-k32": dict(n_shards=512, lo=2000, hi=200_000, c_lo=10, c_hi=500,
                                   bits=256, p=0.2, seed=3, K=32),
     "clustered-4m-512b-k100": dict(n=4_000_000, bits=512, n_centres=20_000, p=0.25, seed=4,
-                                   K=100, row_block=250_000, col_block=131072),
+                                   K=100, row_block=250_000, col_block=262144),
     "gmm-1m-512d": dict(n=1_000_000, d=512, n_comp=1000, centre_std=2.0, seed=5,
                         proj_seed=6, code_bits=256, K_train=32, K_eval=64,
                         train_rows=100_000, eval_queries=10_000),

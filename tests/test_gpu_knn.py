@@ -132,9 +132,9 @@ def test_clustered_20k_128b_k32_full():
 
 def test_clustered_1m_256b_k64_sampled():
     """1,000,000 codes of 256 bits from 1,000 centres (flip 0.2), K = 64, built in
-    131072 x 131072 blocks with merged per-block lists, as timed by the
-    benchmark. Both paths agree on every row; the oracle checks sampled rows
-    (block edges, ends, and random rows)."""
+    the benchmark's blocks (131,072 rows x 262,144 columns), merged across
+    column blocks. Both paths agree on every row; the oracle checks sampled
+    rows (row-tile and block edges, ends, and random rows)."""
     w = datagen.WORKLOADS["clustered-1m-256b-k64"]
     codes = datagen.clustered_codes(w["n"], w["bits"], w["n_centres"], w["p"], w["seed"])
     K, n = w["K"], w["n"]
@@ -143,7 +143,9 @@ def test_clustered_1m_256b_k64_sampled():
     b = gpu_knn(codes, K, POPC, **kw)
     assert_same(a, b, "mfma vs popc")
     g = np.random.default_rng(99)
-    edges = [0, 1, 131071, 131072, 131073, 2 * 131072 - 1, n - 131072, n - 2, n - 1]
+    cb = w["col_block"]
+    edges = [0, 1, 255, 256, 131071, 131072, 131073, cb - 1, cb, 2 * cb - 1, n - cb, n - 257,
+             n - 2, n - 1]
     rows = np.unique(np.concatenate([edges, g.choice(n, 300, replace=False)])).astype(np.uint32)
     want = oracle.knn_rows(codes, K, rows=rows)
     assert_same((a[0][rows], a[1][rows]), want, "oracle rows")
