@@ -99,7 +99,9 @@ typedef struct bdg_knn_opts {
  *   bits    code length, a multiple of 64, at most BDG_MAX_BITS
  *   K       neighbours per row, 1..BDG_MAX_K
  *   out_idx [n][K] uint32, out_dist [n][K] uint16, device
- * Runs on the default stream and returns after completion.
+ * Runs on the default stream and returns after completion. It allocates its
+ * workspace itself and, on the matrix-core path, checks the persistent
+ * launch's stall flag afterwards (BDG_EDEVICE if set; never in a correct run).
  */
 int bdg_build_knn(const uint64_t *codes, uint32_t n, uint32_t bits, uint32_t K,
                   uint32_t *out_idx, uint16_t *out_dist);

@@ -295,11 +295,47 @@ int bdg_build_knn_ex(const uint64_t* codes, uint32_t n, uint32_t bits, uint32_t 
 
 int bdg_build_knn(const uint64_t* codes, uint32_t n, uint32_t bits, uint32_t K, uint32_t* out_idx,
                   uint16_t* out_dist) {
-  int st = bdg_build_knn_ex(codes, n, bits, K, out_idx, out_dist, nullptr, nullptr);
-  if (st != BDG_OK || n == 0) return st;
-  hipError_t e = hipStreamSynchronize(nullptr);
-  if (e != hipSuccess) return device_error(e, "synchronize");
-  return BDG_OK;
+  g_last_error.clear();
+  Plan p;
+  int st = make_plan(n, bits, K, nullptr, &p);
+  if (st != BDG_OK) return st;
+  if (n == 0) return BDG_OK;
+  if (!codes || !out_idx || !out_dist) return set_error(BDG_EINVAL, "null device pointer");
+  // The call owns the workspace, so that after completion it can read the
+  // persistent launch's stall flag.
+  void* ws = nullptr;
+  if (p.ws_bytes) {
+    if (forced_alloc_failure())
+      return set_error(BDG_ENOMEM, "workspace allocation failed (forced by test hook)");
+    if (hipMalloc(&ws, p.ws_bytes) != hipSuccess || !ws) {
+      (void)hipGetLastError();
+      return set_error(BDG_ENOMEM, "workspace allocation of %zu bytes failed", p.ws_bytes);
+    }
+  }
+  bdg_knn_opts o;
+  memset(&o, 0, sizeof o);
+  o.struct_size = sizeof o;
+  o.workspace = ws;
+  o.workspace_bytes = p.ws_bytes;
+  st = bdg_build_knn_ex(codes, n, bits, K, out_idx, out_dist, &o, nullptr);
+  if (st == BDG_OK) {
+    hipError_t e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) {
+      st = device_error(e, "synchronize");
+    } else if (p.running) {
+      uint32_t stall = 0;
+      e = hipMemcpy(&stall,
+                    static_cast<char*>(ws) + p.ws_ctl_off + 4 * bdg::kSweepStallWord,
+                    sizeof stall, hipMemcpyDeviceToHost);
+      if (e != hipSuccess)
+        st = device_error(e, "stall flag read");
+      else if (stall)
+        st = set_error(BDG_EDEVICE,
+                       "a dependency wait of the persistent build ran out; lists unspecified");
+    }
+  }
+  if (ws) (void)hipFree(ws);
+  return st;
 }
 
 int bdg_merge_lists(const uint32_t* in_idx, const uint16_t* in_dist, uint32_t n, uint32_t L,

@@ -149,6 +149,41 @@ def test_sharded_workload_scaled():
     plan.close()
 
 
+def test_sharded_workload_full_sampled():
+    """The many-shards workload at its full size (512 shards, 20,744,181 codes
+    of 256 bits, K = 32), built as the benchmark times it: one plan whose
+    persistent launch is captured in a HIP graph, then replayed. Every shard is
+    checked against the oracle on seeded rows (its first and last, three random
+    ones), after the replay."""
+    import torch
+    w = datagen.WORKLOADS["sharded-512x-256b-k32"]
+    codes, offsets = datagen.sharded_codes(**{k: v for k, v in w.items() if k != "K"})
+    K = w["K"]
+    plan = bdg.BatchPlan(offsets, w["bits"], K)
+    d = dev(codes)
+    stream = torch.cuda.Stream()
+    out = plan.outputs()
+    for rep in range(2):  # captured, then replayed: the replay must rewrite every row
+        out[0].fill_(-3)
+        torch.cuda.synchronize()
+        plan.build(d, out=out, stream=stream, graph=True)
+        stream.synchronize()
+    g = np.random.default_rng(512)
+    sizes = np.diff(offsets.astype(np.int64))
+    local = [np.unique(np.r_[0, n_s - 1, g.integers(0, n_s, 3)]) for n_s in sizes.tolist()]
+    rows = np.concatenate([int(offsets[s]) + r for s, r in enumerate(local)])
+    sel = torch.from_numpy(rows.astype(np.int64)).cuda()
+    gi, gd = to_np((out[0][sel], out[1][sel]))
+    pos = 0
+    for s, r in enumerate(local):
+        lo, hi = int(offsets[s]), int(offsets[s + 1])
+        wi, wd = oracle.knn_rows(codes[lo:hi], K, rows=r.astype(np.uint32))
+        assert np.array_equal(gi[pos:pos + r.size], wi) and np.array_equal(gd[pos:pos + r.size], wd), \
+            f"shard {s} ({hi - lo} rows), rows {r.tolist()}"
+        pos += r.size
+    plan.close()
+
+
 def test_autotune_build_keeps_the_graph():
     import torch
     codes = datagen.clustered_codes(20_000, 128, 100, 0.15, seed=1)

@@ -151,6 +151,25 @@ def test_clustered_1m_256b_k64_sampled():
     assert_same((a[0][rows], a[1][rows]), want, "oracle rows")
 
 
+def test_clustered_4m_512b_k100_sampled():
+    """4,000,000 codes of 512 bits from 20,000 centres (flip 0.25), K = 100
+    (lists of 128 keys, row tiles of 192 rows), built as the benchmark times
+    it: one persistent launch over column blocks of 262,144. The oracle checks
+    sampled rows: row-tile and column-block edges, the ends, random rows."""
+    import torch
+    w = datagen.WORKLOADS["clustered-4m-512b-k100"]
+    codes = datagen.clustered_codes(w["n"], w["bits"], w["n_centres"], w["p"], w["seed"])
+    K, n, cb = w["K"], w["n"], w["col_block"]
+    idx, dist = bdg.build_knn(dev(codes), K, path=MFMA, row_block=w["row_block"], col_block=cb)
+    g = np.random.default_rng(100)
+    edges = [0, 1, 191, 192, cb - 1, cb, 2 * cb, n - cb, n - 193, n - 192, n - 1]
+    rows = np.unique(np.concatenate([edges, g.choice(n, 150, replace=False)])).astype(np.int64)
+    sel = torch.from_numpy(rows).cuda()
+    got = bdg.to_numpy_graph(idx[sel], dist[sel])
+    want = oracle.knn_rows(codes, K, rows=rows.astype(np.uint32))
+    assert_same(got, want, "4M x 512 bits, sampled rows")
+
+
 # ----------------------------------------------------------------- merge
 
 def test_merge_golden():
@@ -225,6 +244,7 @@ def test_caller_workspace_and_alloc_failure():
     try:
         o2 = bdg.make_opts(col_block=600)
         assert bdg.bdg_build_knn_ex(d, 2500, 128, K, idx, dist, o2, None) == bdg.BDG_ENOMEM
+        assert bdg.bdg_build_knn(d, 2500, 128, K, idx, dist) == bdg.BDG_ENOMEM
     finally:
         del os.environ["BDG_TEST_FAIL_ALLOC"]
     torch.cuda.synchronize()
