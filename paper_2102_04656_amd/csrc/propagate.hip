@@ -161,27 +161,41 @@ __global__ __launch_bounds__(256) void propagate_kernel(const uint64_t* __restri
   }
   uint32_t maxd = kth_dist();
 
-  // Second floor: the lists of the first-floor neighbours.
+  // Second floor: the lists of the first-floor neighbours, two neighbours at
+  // a time (both list chunks, then both chunks' codes, are gathered before
+  // either is filtered, so each pair costs one round of dependent loads).
+  // The second chunk is filtered again after the first one's merge; a filter
+  // with an older, larger K-th distance only admits more, so it stays exact.
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
-    for (uint32_t tt = 0; tt < (uint32_t)kPW; ++tt) {
+    for (uint32_t tt = 0; tt < (uint32_t)kPW; tt += 2) {
       const uint32_t t = r * kPW + tt;
       if (t >= K) break;
-      const uint32_t y = __builtin_amdgcn_readlane(yv[r], tt);
-      if (y == kAbsent) continue;  // wave-uniform
-      const size_t ybase = (size_t)y * K;
+      const uint32_t ya = __builtin_amdgcn_readlane(yv[r], tt);
+      const uint32_t yb = t + 1 < K ? __builtin_amdgcn_readlane(yv[r], tt + 1) : kAbsent;
+      if (ya == kAbsent && yb == kAbsent) continue;  // wave-uniform
       for (uint32_t c0 = 0; c0 < K; c0 += kPW) {
         const uint32_t p = c0 + lane;
-        const uint32_t z = p < K ? in_idx[ybase + p] : kAbsent;
-        const bool valid = z != kAbsent && z < n && z != row;
-        const uint32_t ins = valid ? set_insert(set, z) : 0u;
-        if (__any(ins == 2u)) exact_set = false;
-        const bool ok = ins != 0u;
-        const uint32_t h = ok ? ham_to(z) : 0xFFFFFFFFu;
-        const bool pass = ok && h <= maxd;
-        if (!__any(pass)) continue;
-        absorb(pass ? (((uint64_t)h << 32) | z) : kNone64, !exact_set);
-        maxd = kth_dist();
+        const uint32_t za = (ya != kAbsent && p < K) ? in_idx[(size_t)ya * K + p] : kAbsent;
+        const uint32_t zb = (yb != kAbsent && p < K) ? in_idx[(size_t)yb * K + p] : kAbsent;
+        const bool va = za != kAbsent && za < n && za != row;
+        const bool vb = zb != kAbsent && zb < n && zb != row;
+        const uint32_t insa = va ? set_insert(set, za) : 0u;
+        const uint32_t insb = vb ? set_insert(set, zb) : 0u;
+        if (__any(insa == 2u || insb == 2u)) exact_set = false;
+        const bool oka = insa != 0u, okb = insb != 0u;
+        const uint32_t ha = oka ? ham_to(za) : 0xFFFFFFFFu;
+        const uint32_t hb = okb ? ham_to(zb) : 0xFFFFFFFFu;
+        const bool pa = oka && ha <= maxd;
+        if (__any(pa)) {
+          absorb(pa ? (((uint64_t)ha << 32) | za) : kNone64, !exact_set);
+          maxd = kth_dist();
+        }
+        const bool pb = okb && hb <= maxd;
+        if (__any(pb)) {
+          absorb(pb ? (((uint64_t)hb << 32) | zb) : kNone64, !exact_set);
+          maxd = kth_dist();
+        }
       }
     }
   }
