@@ -17,7 +17,7 @@
 // pairs the same code bit of both operands (A and B share the lane-to-k map).
 //
 // Work split. A work-group has NW compute waves; each owns 16 QG queries
-// (rows) held as B operands in registers for the whole launch. They share a
+// (rows) held as B operands in registers for the whole job. They share a
 // stream of candidate stages (CT codes each) copied from HBM straight into a
 // ring of LDS slots (one copy per work-group) and read back as A operands.
 // With K <= 64 there are 8 compute waves of 32 queries, two on each SIMD: the
@@ -36,11 +36,13 @@
 //
 // Lists. Keys are dist << IB | column (global column index, IB = 32 - bits
 // needed for a distance), so key order is the (distance, index) order of the
-// graph. Each launch covers one column block [cb, ce); the lists of its rows
-// are read from the output at the start (the merged result of the earlier
-// column blocks, Sec. 3.2 second reduce) and written back at the end. Columns
-// arrive in increasing index, so an equal distance never displaces a kept
-// key: the strict test ham < thr is exact.
+// graph. Each job covers one column block [cb, ce): one launch of the run
+// kernel, or one work item of the persistent build, which takes a row tile's
+// column blocks in order. The lists of its rows are read from the output at
+// the start (the merged result of the earlier column blocks, Sec. 3.2 second
+// reduce) and written back at the end. Columns arrive in increasing index, so
+// an equal distance never displaces a kept key: the strict test ham < thr is
+// exact.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
