@@ -133,8 +133,8 @@ def test_clustered_20k_128b_k32_full():
 def test_clustered_1m_256b_k64_sampled():
     """1,000,000 codes of 256 bits from 1,000 centres (flip 0.2), K = 64, built in
     the benchmark's blocks (131,072 rows x 262,144 columns), merged across
-    column blocks. Both paths agree on every row; the oracle checks sampled
-    rows (row-tile and block edges, ends, and random rows)."""
+    column blocks. Both paths agree on every row; the oracle checks 4,096
+    seeded rows plus the row-tile and block edges and the ends."""
     w = datagen.WORKLOADS["clustered-1m-256b-k64"]
     codes = datagen.clustered_codes(w["n"], w["bits"], w["n_centres"], w["p"], w["seed"])
     K, n = w["K"], w["n"]
@@ -146,7 +146,7 @@ def test_clustered_1m_256b_k64_sampled():
     cb = w["col_block"]
     edges = [0, 1, 255, 256, 131071, 131072, 131073, cb - 1, cb, 2 * cb - 1, n - cb, n - 257,
              n - 2, n - 1]
-    rows = np.unique(np.concatenate([edges, g.choice(n, 300, replace=False)])).astype(np.uint32)
+    rows = np.unique(np.concatenate([edges, g.choice(n, 4096, replace=False)])).astype(np.uint32)
     want = oracle.knn_rows(codes, K, rows=rows)
     assert_same((a[0][rows], a[1][rows]), want, "oracle rows")
 
@@ -155,7 +155,7 @@ def test_clustered_4m_512b_k100_sampled():
     """4,000,000 codes of 512 bits from 20,000 centres (flip 0.25), K = 100
     (lists of 128 keys, row tiles of 192 rows), built as the benchmark times
     it: one persistent launch over column blocks of 262,144. The oracle checks
-    sampled rows: row-tile and column-block edges, the ends, random rows."""
+    4,096 seeded rows plus the row-tile and column-block edges and the ends."""
     import torch
     w = datagen.WORKLOADS["clustered-4m-512b-k100"]
     codes = datagen.clustered_codes(w["n"], w["bits"], w["n_centres"], w["p"], w["seed"])
@@ -163,7 +163,7 @@ def test_clustered_4m_512b_k100_sampled():
     idx, dist = bdg.build_knn(dev(codes), K, path=MFMA, row_block=w["row_block"], col_block=cb)
     g = np.random.default_rng(100)
     edges = [0, 1, 191, 192, cb - 1, cb, 2 * cb, n - cb, n - 193, n - 192, n - 1]
-    rows = np.unique(np.concatenate([edges, g.choice(n, 150, replace=False)])).astype(np.int64)
+    rows = np.unique(np.concatenate([edges, g.choice(n, 4096, replace=False)])).astype(np.int64)
     sel = torch.from_numpy(rows).cuda()
     got = bdg.to_numpy_graph(idx[sel], dist[sel])
     want = oracle.knn_rows(codes, K, rows=rows.astype(np.uint32))
