@@ -578,11 +578,13 @@ constexpr int stage_groups(int W, int NR) {
 constexpr size_t state_bytes(int K, int qg, int nw) {
   return (size_t)nw * ((size_t)16 * qg * K + (size_t)16 * qg * kBuf + 64) * 4;
 }
-// Stage slots: with a producer as many as the LDS left by the largest lists of
-// the class holds (at most 8); without, the previous fixed depths.
-constexpr int stages_of(int W, int NR) {
+// Stage slots: with a producer as many as the LDS left by lists of KC keys
+// holds (at most 8); without, the previous fixed depths. KC is the list
+// capacity class of K (kc_of): shorter lists leave room for more stages in
+// flight, which the producer needs to cover the load latency of the stream.
+constexpr int stages_of(int W, int NR, int KC) {
   if (!use_producer(W, NR)) return NR == 2 ? 2 : 3;
-  const size_t avail = 160 * 1024 - state_bytes(64 * NR, qgroups_of_nr(NR), waves_of_nr(NR)) - 256;
+  const size_t avail = 160 * 1024 - state_bytes(KC, qgroups_of_nr(NR), waves_of_nr(NR)) - 256;
   const size_t n = avail / ((size_t)stage_groups(W, NR) * W * 1024);
   return n > 8 ? 8 : (int)n;
 }
@@ -709,6 +711,11 @@ __global__ void zero_words_kernel(uint32_t* w, uint32_t count) {
 }  // namespace
 
 inline int nr_of(uint32_t K) { return K <= 64 ? 1 : (K <= 128 ? 2 : 4); }
+// List capacity class: the stage ring of a launch is sized for lists of this
+// many keys (at least K).
+inline int kc_of(uint32_t K) {
+  return K <= 32 ? 32 : (K <= 64 ? 64 : (K <= 112 ? 112 : (K <= 128 ? 128 : 256)));
+}
 inline int qg_of(uint32_t K) { return qgroups_of_nr(nr_of(K)); }
 inline int nw_of(uint32_t K) { return waves_of_nr(nr_of(K)); }
 
@@ -716,14 +723,14 @@ inline size_t run_state_bytes(uint32_t K, int qg) { return state_bytes((int)K, q
 
 inline size_t run_lds_bytes(uint32_t W, uint32_t K) {
   const size_t stage = (size_t)stage_groups((int)W, nr_of(K)) * W * 1024;
-  return stages_of((int)W, nr_of(K)) * stage + run_state_bytes(K, qg_of(K));
+  return stages_of((int)W, nr_of(K), kc_of(K)) * stage + run_state_bytes(K, qg_of(K));
 }
 
-template <int W, int NR>
+template <int W, int NR, int KC>
 inline hipError_t launch_run_w(const RunArgs& a, hipStream_t stream) {
   constexpr int QG = qgroups_of_nr(NR);
   constexpr int GPS = stage_groups(W, NR);
-  constexpr int NST = stages_of(W, NR);
+  constexpr int NST = stages_of(W, NR, KC);
   static_assert(NST >= 2, "stage ring needs two slots");
   // the rectangular variant exists for lists of up to 64 keys only
   auto kern = knn_mfma_run_kernel<W, NR, QG, GPS, NST>;
@@ -753,11 +760,11 @@ inline hipError_t launch_run_w(const RunArgs& a, hipStream_t stream) {
   return hipGetLastError();
 }
 
-template <int W, int NR>
+template <int W, int NR, int KC>
 inline hipError_t launch_batched_w(const BatchArgs& a, hipStream_t stream) {
   constexpr int QG = qgroups_of_nr(NR);
   constexpr int GPS = stage_groups(W, NR);
-  constexpr int NST = stages_of(W, NR);
+  constexpr int NST = stages_of(W, NR, KC);
   static_assert(NST >= 2, "stage ring needs two slots");
   auto kern = knn_mfma_batched_kernel<W, NR, QG, GPS, NST>;
   const size_t lds = run_state_bytes(a.K, QG);
@@ -771,11 +778,11 @@ inline hipError_t launch_batched_w(const BatchArgs& a, hipStream_t stream) {
   return hipGetLastError();
 }
 
-template <int W, int NR>
+template <int W, int NR, int KC>
 inline hipError_t launch_sweep_w(const SweepArgs& a, hipStream_t stream) {
   constexpr int QG = qgroups_of_nr(NR);
   constexpr int GPS = stage_groups(W, NR);
-  constexpr int NST = stages_of(W, NR);
+  constexpr int NST = stages_of(W, NR, KC);
   static_assert(NST >= 2, "stage ring needs two slots");
   auto kern = knn_mfma_sweep_kernel<W, NR, QG, GPS, NST>;
   const size_t lds = run_state_bytes(a.K, QG);
@@ -800,28 +807,34 @@ inline hipError_t launch_sweep_w(const SweepArgs& a, hipStream_t stream) {
 
 template <int W>
 inline hipError_t launch_sweep_nr(const SweepArgs& a, hipStream_t stream) {
-  switch (nr_of(a.K)) {
-    case 1: return launch_sweep_w<W, 1>(a, stream);
-    case 2: return launch_sweep_w<W, 2>(a, stream);
-    default: return launch_sweep_w<W, 4>(a, stream);
+  switch (kc_of(a.K)) {
+    case 32: return launch_sweep_w<W, 1, 32>(a, stream);
+    case 64: return launch_sweep_w<W, 1, 64>(a, stream);
+    case 112: return launch_sweep_w<W, 2, 112>(a, stream);
+    case 128: return launch_sweep_w<W, 2, 128>(a, stream);
+    default: return launch_sweep_w<W, 4, 256>(a, stream);
   }
 }
 
 template <int W>
 inline hipError_t launch_batched_nr(const BatchArgs& a, hipStream_t stream) {
-  switch (nr_of(a.K)) {
-    case 1: return launch_batched_w<W, 1>(a, stream);
-    case 2: return launch_batched_w<W, 2>(a, stream);
-    default: return launch_batched_w<W, 4>(a, stream);
+  switch (kc_of(a.K)) {
+    case 32: return launch_batched_w<W, 1, 32>(a, stream);
+    case 64: return launch_batched_w<W, 1, 64>(a, stream);
+    case 112: return launch_batched_w<W, 2, 112>(a, stream);
+    case 128: return launch_batched_w<W, 2, 128>(a, stream);
+    default: return launch_batched_w<W, 4, 256>(a, stream);
   }
 }
 
 template <int W>
 inline hipError_t launch_run_nr(const RunArgs& a, hipStream_t stream) {
-  switch (nr_of(a.K)) {
-    case 1: return launch_run_w<W, 1>(a, stream);
-    case 2: return launch_run_w<W, 2>(a, stream);
-    default: return launch_run_w<W, 4>(a, stream);
+  switch (kc_of(a.K)) {
+    case 32: return launch_run_w<W, 1, 32>(a, stream);
+    case 64: return launch_run_w<W, 1, 64>(a, stream);
+    case 112: return launch_run_w<W, 2, 112>(a, stream);
+    case 128: return launch_run_w<W, 2, 128>(a, stream);
+    default: return launch_run_w<W, 4, 256>(a, stream);
   }
 }
 

@@ -67,6 +67,11 @@ GRID = [
     (777, 448, 128, 7, 0.2),
     (600, 576, 256, 6, 0.2),
     (3001, 256, 7, 40, 0.2),
+    # list capacity classes at their bounds (stage rings of 5, 3, 2 and 6 slots)
+    (1500, 256, 32, 15, 0.2),
+    (900, 512, 112, 9, 0.25),
+    (1200, 256, 120, 12, 0.2),
+    (1100, 128, 96, 11, 0.15),
 ]
 
 
