@@ -156,6 +156,22 @@ def test_clustered_1m_256b_k64_sampled():
     assert_same((a[0][rows], a[1][rows]), want, "oracle rows")
 
 
+@pytest.mark.skipif(os.environ.get("BDG_FULL_PARITY") != "1",
+                    reason="every row of the 1M graph against the C oracle: about 1e12 pairs, "
+                           "minutes of CPU; set BDG_FULL_PARITY=1")
+def test_clustered_1m_256b_k64_every_row():
+    """The whole 1,000,000-row graph of the benchmark workload (exact K = 64,
+    built as the benchmark times it) equals the C oracle's on every row."""
+    w = datagen.WORKLOADS["clustered-1m-256b-k64"]
+    codes = datagen.clustered_codes(w["n"], w["bits"], w["n_centres"], w["p"], w["seed"])
+    got = gpu_knn(codes, w["K"], MFMA, row_block=w["row_block"], col_block=w["col_block"])
+    n = w["n"]
+    for part, rows in enumerate(np.array_split(np.arange(n, dtype=np.uint32), 8)):
+        want = oracle.knn_rows(codes, w["K"], rows=rows)
+        assert_same((got[0][rows], got[1][rows]), want, f"1M rows {rows[0]}..{rows[-1]}")
+        print(f"[every-row] part {part + 1}/8 identical", flush=True)
+
+
 def test_clustered_4m_512b_k100_sampled():
     """4,000,000 codes of 512 bits from 20,000 centres (flip 0.25), K = 100
     (lists of 128 keys, row tiles of 192 rows), built as the benchmark times
