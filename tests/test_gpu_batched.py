@@ -3,6 +3,8 @@ the autotuner: every shard's graph, with shard-local indices, equals the CPU
 oracle on that shard alone, bit for bit; work orders, HIP-graph replays and
 tuned schedules give the same graph.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -183,6 +185,24 @@ def test_sharded_workload_full_sampled():
         assert np.array_equal(gi[pos:pos + r.size], wi) and np.array_equal(gd[pos:pos + r.size], wd), \
             f"shard {s} ({hi - lo} rows), rows {r.tolist()}"
         pos += r.size
+    plan.close()
+
+
+@pytest.mark.skipif(os.environ.get("BDG_FULL_PARITY") != "1",
+                    reason="every row of the 512 shards against the C oracle: 1.9e12 pairs, "
+                           "minutes of CPU; set BDG_FULL_PARITY=1")
+def test_sharded_workload_every_row():
+    """The whole graph of the 512-shard workload equals the C oracle's, shard by
+    shard, on every row."""
+    w = datagen.WORKLOADS["sharded-512x-256b-k32"]
+    codes, offsets = datagen.sharded_codes(**{k: v for k, v in w.items() if k != "K"})
+    plan = bdg.BatchPlan(offsets, w["bits"], w["K"])
+    gi, gd = to_np(plan.build(dev(codes)))
+    order = np.argsort(np.diff(offsets.astype(np.int64)))
+    for i, s in enumerate(order.tolist()):
+        check_shard(gi, gd, codes, offsets, s, w["K"])
+        if (i + 1) % 64 == 0 or int(offsets[s + 1] - offsets[s]) > 100_000:
+            print(f"[every-row] {i + 1}/512 shards identical", flush=True)
     plan.close()
 
 

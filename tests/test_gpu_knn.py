@@ -175,13 +175,19 @@ def test_clustered_1m_256b_k64_every_row():
 def test_clustered_4m_512b_k100_sampled():
     """4,000,000 codes of 512 bits from 20,000 centres (flip 0.25), K = 100
     (lists of 128 keys, row tiles of 192 rows), built as the benchmark times
-    it: one persistent launch over column blocks of 262,144. The oracle checks
-    4,096 seeded rows plus the row-tile and column-block edges and the ends."""
+    it: one persistent launch over column blocks of 262,144. The vector-ALU
+    path gives the same graph on every row; the oracle checks 4,096 seeded rows
+    plus the row-tile and column-block edges and the ends."""
     import torch
     w = datagen.WORKLOADS["clustered-4m-512b-k100"]
     codes = datagen.clustered_codes(w["n"], w["bits"], w["n_centres"], w["p"], w["seed"])
     K, n, cb = w["K"], w["n"], w["col_block"]
-    idx, dist = bdg.build_knn(dev(codes), K, path=MFMA, row_block=w["row_block"], col_block=cb)
+    d = dev(codes)
+    idx, dist = bdg.build_knn(d, K, path=MFMA, row_block=w["row_block"], col_block=cb)
+    pi, pd = bdg.build_knn(d, K, path=POPC, row_block=w["row_block"], col_block=cb)
+    torch.cuda.synchronize()
+    assert torch.equal(idx, pi) and torch.equal(dist, pd), "matrix-core and vector-ALU graphs differ"
+    del pi, pd
     g = np.random.default_rng(100)
     edges = [0, 1, 191, 192, cb - 1, cb, 2 * cb, n - cb, n - 193, n - 192, n - 1]
     rows = np.unique(np.concatenate([edges, g.choice(n, 4096, replace=False)])).astype(np.int64)
