@@ -352,6 +352,45 @@ def dac_leg(codes_dev, exact, bits, K, m=1024, iters=8, T=16, coarse_num=8192):
     return res
 
 
+def batched_popc_leg(d, offsets, sizes, bits, K, pairs, out, stream):
+    """The vector-ALU path on the same shards: one bdg_build_knn_ex per shard
+    (shard-local indices by construction), one untimed and one timed pass;
+    its graph is compared with the batched launch's on every row."""
+    import torch
+    from paper_2102_04656_amd import bdg
+    pi, pd = torch.empty_like(out[0]), torch.empty_like(out[1])
+    nmax = int(sizes.max())
+    ws_bytes = bdg.bdg_build_knn_workspace_size(nmax, bits, K, bdg.make_opts(path=bdg.PATH_POPC))
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device="cuda")
+    o = bdg.make_opts(path=bdg.PATH_POPC, workspace=ws.data_ptr(), workspace_bytes=ws_bytes)
+
+    def one_pass():
+        for s in range(len(sizes)):
+            lo, hi = int(offsets[s]), int(offsets[s + 1])
+            if hi > lo:
+                st = bdg.bdg_build_knn_ex(d[lo:hi], hi - lo, bits, K, pi[lo:hi], pd[lo:hi], o,
+                                          stream)
+                if st != 0:
+                    raise RuntimeError(f"shard {s}: bdg_build_knn_ex failed: {st} "
+                                       f"{bdg.last_error()}")
+
+    log("[bench] vector-ALU path, one build per shard")
+    one_pass()
+    stream.synchronize()
+    t0 = time.perf_counter()
+    one_pass()
+    stream.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    same = bool(torch.equal(pi, out[0]) and torch.equal(pd, out[1]))
+    ops = pairs * 2 * bits // 32
+    log(f"[bench] vector-ALU path: {ms:.1f} ms, graph identical to the batched launch: {same}")
+    return {"value": pairs / (ms * 1e-3), "ms_per_step": ms, "steps": 1,
+            "kernel": "knn_popc_kernel + merge_lists_kernel, one bdg_build_knn_ex per shard",
+            "achieved": ops / (ms * 1e-3) / 1e12, "peak": PEAK_VALU_TOPS, "unit": "T ops/s",
+            "frac": ops / (ms * 1e-3) / 1e12 / PEAK_VALU_TOPS, "timing": "end to end, host clock",
+            "identical_to_batched_graph": same}
+
+
 def bench_batched(args, w):
     """Many shards in one persistent launch, replayed as a HIP graph (schedule
     autotuned once, outside the timed region)."""
@@ -415,6 +454,8 @@ def bench_batched(args, w):
         result["roofline"]["traffic_source"] = (
             f"profiles/traffic__knn_mfma_batched_kernel__{args.workload}.md (FETCH_SIZE + "
             f"WRITE_SIZE per launch, copy-calibrated)")
+    if args.other_path:
+        result["popc_path"] = batched_popc_leg(d, offsets, sizes, bits, K, pairs, out, stream)
     if args.copy_calibration:
         copy_calibration()
     if not args.no_cpu_baseline:
