@@ -393,7 +393,8 @@ def l2_f32(a: np.ndarray, b: np.ndarray) -> np.float32:
 
 
 def graph_search(codes: np.ndarray, graph_idx: np.ndarray, feats: np.ndarray, q_code, q_feat,
-                 entries, P: int, N: int, exclude=None, max_expand: int = 1 << 20):
+                 entries, P: int, N: int, exclude=None, max_expand: int = 1 << 20,
+                 trace: dict | None = None):
     """One query of the online search (Sec. 3.5).
 
     Entry point: the nearest of the sampled rows ``entries`` to the query
@@ -406,7 +407,9 @@ def graph_search(codes: np.ndarray, graph_idx: np.ndarray, feats: np.ndarray, q_
     ``exclude`` (the query's own row) is never measured. Re-rank: all pool
     members by ``l2_f32`` to the query's features, ties to the smaller
     index; returns (idx [N], dist float32 [N]) padded with (0xFFFFFFFF,
-    inf), and the number of rows visited.
+    inf), and the number of rows visited. If ``trace`` is a dict, it
+    receives the expanded rows in order ("expand") and the final pool of
+    (ham, idx) keys ("pool").
     """
     codes = np.ascontiguousarray(codes, dtype=np.uint64)
     n = codes.shape[0]
@@ -437,6 +440,8 @@ def graph_search(codes: np.ndarray, graph_idx: np.ndarray, feats: np.ndarray, q_
             break
         u = cand[0][1]
         expanded.add(u)
+        if trace is not None:
+            trace.setdefault("expand", []).append(u)
         steps += 1
         for v in [int(x) for x in graph_idx[u]]:
             if v == NO_IDX or v >= n or v in visited:
@@ -444,6 +449,8 @@ def graph_search(codes: np.ndarray, graph_idx: np.ndarray, feats: np.ndarray, q_
             visited.add(v)
             pool.append((ham(v), v))
         pool = sorted(pool)[:P]
+    if trace is not None:
+        trace["pool"] = list(pool)
     rr = sorted((l2_f32(feats[j], q_feat), j) for _, j in pool)[:N]
     for k, (d, j) in enumerate(rr):
         out_idx[k] = j

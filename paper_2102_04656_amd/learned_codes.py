@@ -115,11 +115,18 @@ def train_encoder(x_train, knn_idx, scale: float, bits: int = 256, h: int = 1024
 
 
 def recall_at(graph_idx, exact_idx, N: int) -> float:
-    """Eq. 3 on GPU tensors: mean over rows of |graph[:N] ∩ exact[:N]| / N."""
+    """Eq. 3 on GPU tensors: mean over rows of |graph[:N] ∩ exact[:N]| / N,
+    as sets: each distinct entry of the exact row that the graph row holds
+    counts once (a repeated graph entry does not count twice)."""
+    import torch
     g = graph_idx[:, :N].long()
     e = exact_idx[:, :N].long()
-    hits = (g[:, :, None] == e[:, None, :]).any(dim=2).sum(dim=1)
-    return float(hits.float().mean().item()) / N
+    first = torch.ones_like(e, dtype=torch.bool)
+    if N > 1:  # an entry repeated within the exact row counts at its first place only
+        same = e[:, :, None] == e[:, None, :]
+        first = ~torch.tril(same, diagonal=-1).any(dim=2)
+    hits = ((e[:, :, None] == g[:, None, :]).any(dim=2) & first).sum(dim=1)
+    return float(hits.double().mean().item()) / N
 
 
 class Workload:

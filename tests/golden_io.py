@@ -73,3 +73,46 @@ def merge_small():
     out_idx = np.array([[p[1] for p in outs[r]] for r in range(n)], dtype=np.uint32)
     out_dist = np.array([[p[0] for p in outs[r]] for r in range(n)], dtype=np.uint16)
     return K, in_idx, in_dist, out_idx, out_dist
+
+
+def search_small():
+    """-> (codes [n][1] uint64, graph [n][K] uint32, feats [n][d] float32,
+    entries, cases) from search_small.txt; each case is a dict with P, N,
+    exclude (None or a row), expand (rows in order), pool [(ham, idx)],
+    visited and answer [(idx, dist)]."""
+    nodes, graph, feats, entries, cases = {}, {}, {}, None, {}
+    for line in _lines("search_small.txt"):
+        line = line.split("#", 1)[0].strip()
+        if not line or line.startswith("bits"):
+            continue
+        head, _, body = line.partition(":")
+        parts = head.split()
+        if parts[0] == "node":
+            nodes[int(parts[1])] = [] if body.strip() == "-" else [int(t) for t in body.split()]
+        elif parts[0] == "graph":
+            graph[int(parts[1])] = [int(t) for t in body.split()]
+        elif parts[0] == "feat":
+            feats[int(parts[1])] = [float(t) for t in body.split()]
+        elif parts[0] == "entries":
+            entries = [int(t) for t in parts[1:]]
+        elif parts[0] == "case":
+            kv = dict(tok.split("=") for tok in parts[2:])
+            cases[parts[1]] = dict(P=int(kv["P"]), N=int(kv["N"]),
+                                   exclude=None if kv["exclude"] == "-" else int(kv["exclude"]))
+        elif parts[0] == "expand":
+            cases[parts[1]]["expand"] = [int(t) for t in body.split()]
+        elif parts[0] == "pool":
+            cases[parts[1]]["pool"] = [tuple(int(v) for v in t.split(",")) for t in body.split()]
+        elif parts[0] == "visited":
+            cases[parts[1]]["visited"] = int(body)
+        elif parts[0] == "answer":
+            cases[parts[1]]["answer"] = [(int(t.split(",")[0]), float(t.split(",")[1]))
+                                         for t in body.split()]
+    n = len(nodes)
+    codes = np.zeros((n, 1), dtype=np.uint64)
+    for i, pos in nodes.items():
+        for b in pos:
+            codes[i, 0] |= np.uint64(1) << np.uint64(b)
+    g = np.array([graph[i] for i in range(n)], dtype=np.uint32)
+    f = np.array([feats[i] for i in range(n)], dtype=np.float32)
+    return codes, g, f, entries, cases

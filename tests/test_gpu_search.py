@@ -72,3 +72,20 @@ def test_search_new_queries():
         oi, od, ov = oracle.graph_search(codes, gi, feats, qc[k], qf[k], entries, P, N)
         assert np.array_equal(gi_i[k], oi) and np.array_equal(gi_d[k].view(np.uint32), od.view(np.uint32))
         assert int(gi_v[k]) == ov
+
+
+def test_search_hand_derived_trace():
+    """The 9-row fixture of tests/golden/search_small.txt (pool of 3 on a
+    graph of 2 neighbours per row): answers, distances and visited counts as
+    derived by hand (the GPU count leaves out the excluded row)."""
+    from tests import golden_io
+    codes, gi, feats, entries, cases = golden_io.search_small()
+    qc = np.zeros((1, 1), dtype=np.uint64)
+    qf = np.zeros((1, feats.shape[1]), dtype=np.float32)
+    for name, c in cases.items():
+        excl = None if c["exclude"] is None else np.array([c["exclude"]], dtype=np.uint32)
+        print(f"[search] fixture case {name}", flush=True)
+        oi, od, ov = run_gpu(codes, gi, feats, qc, qf, excl, np.array(entries, dtype=np.uint32),
+                             c["P"], c["N"])
+        assert [(int(i), float(d)) for i, d in zip(oi[0], od[0])] == c["answer"], name
+        assert int(ov[0]) == c["visited"] - (0 if excl is None else 1), name

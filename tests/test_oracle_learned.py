@@ -167,3 +167,80 @@ def test_adam_first_step_closed_form():
     p, m, v = L.adam_step(np.zeros(3), g, np.zeros(3), np.zeros(3), t=1, lr=0.1)
     # bias-corrected moments equal g and g^2: the step is lr * g / (|g| + eps)
     assert np.allclose(p, -0.1 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+# Adam beyond the first step. With beta1 = 1/2, beta2 = 3/4, lr = 1/10 and
+# eps = 0 the moments and bias corrections are small fractions, worked by hand:
+#   gradients 1, 0, -1:
+#     t=1: m = 1/2,  v = 1/4,    m^ = 1,    v^ = 1      step -1/10
+#     t=2: m = 1/4,  v = 3/16,   m^ = 1/3,  v^ = 3/7    step -(1/3)/sqrt(3/7)/10 = -sqrt(7/27)/10
+#     t=3: m = -3/8, v = 25/64,  m^ = -3/7, v^ = 25/37  step +(3/7)/(5/sqrt(37))/10 = +3 sqrt(37)/350
+#   a constant gradient 2: m^ = 2 and v^ = 4 at every t, so every step is -1/10.
+#   gradients 2, -2, 4:
+#     t=1: m = 1,    v = 1,      m^ = 2,    v^ = 4      step -1/10
+#     t=2: m = -1/2, v = 7/4,    m^ = -2/3, v^ = 4      step +1/30
+#     t=3: m = 7/4,  v = 85/16,  m^ = 2,    v^ = 340/37 step -(2/10) sqrt(37/340)
+_ADAM_G = np.array([[1.0, 2.0, 2.0], [0.0, 2.0, -2.0], [-1.0, 2.0, 4.0]])
+_ADAM_WANT = np.array([
+    [-0.1, -0.1, -0.1],
+    [-0.1 - np.sqrt(7 / 27) / 10, -0.2, -1 / 15],
+    [-0.1 - np.sqrt(7 / 27) / 10 + 3 * np.sqrt(37) / 350, -0.3,
+     -1 / 15 - 0.2 * np.sqrt(37 / 340)],
+])
+
+
+def _adam_pin(step):
+    """Three steps of `step` against the hand-worked parameters, or a
+    description of the first mismatch."""
+    p, m, v = np.zeros(3), np.zeros(3), np.zeros(3)
+    for t in range(1, 4):
+        p, m, v = step(p, _ADAM_G[t - 1], m, v, t=t, lr=0.1, beta1=0.5, beta2=0.75, eps=0.0)
+        if not np.allclose(p, _ADAM_WANT[t - 1], rtol=1e-12, atol=1e-15):
+            return f"t={t}: {p} != {_ADAM_WANT[t - 1]}"
+    return None
+
+
+def test_adam_three_steps_closed_form():
+    assert _adam_pin(L.adam_step) is None
+
+
+def _planted_adam(kind):
+    def step(param, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        m = beta1 * m + (1.0 - beta1) * grad
+        v = beta2 * v + (1.0 - beta2) * grad * grad
+        tc = 1 if kind == "bias_frozen_t1" else t
+        mh = m / (1.0 - beta1 ** tc)
+        vh = v / (1.0 - (beta1 if kind == "beta1_in_v" else beta2) ** tc)
+        if kind == "no_v_correction":
+            vh = v
+        return param - lr * mh / (np.sqrt(vh) + eps), m, v
+    return step
+
+
+@pytest.mark.parametrize("kind", ["bias_frozen_t1", "beta1_in_v", "no_v_correction"])
+def test_adam_pin_catches_planted_mistakes(kind):
+    assert _adam_pin(_planted_adam(kind)) is not None, f"planted mistake {kind} passed"
+
+
+def test_adam_planted_copy_without_mistake_passes():
+    assert _adam_pin(_planted_adam("none")) is None
+
+
+def test_torch_recall_matches_oracle_recall():
+    """The recall the experiment reports (torch, on whatever device the
+    tensors live) equals the oracle's set definition of Eq. 3, including rows
+    with repeated entries and entries beyond N."""
+    import torch
+    from paper_2102_04656_amd import learned_codes
+    g = np.random.default_rng(11)
+    exact = np.stack([g.permutation(200)[:64] for _ in range(300)]).astype(np.int64)
+    approx = exact.copy()
+    for r in range(300):  # replace a random part of each row, some with repeats
+        k = g.integers(0, 65)
+        pos = g.choice(64, size=k, replace=False)
+        approx[r, pos] = g.integers(0, 200, size=k)
+    approx[::7, 1] = approx[::7, 0]  # a repeated graph entry
+    for N in (1, 10, 32, 64):
+        want = L.recall_at(approx, exact, N)
+        got = learned_codes.recall_at(torch.from_numpy(approx), torch.from_numpy(exact), N)
+        assert abs(got - want) < 1e-12, (N, got, want)
