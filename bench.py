@@ -1,22 +1,27 @@
 #!/usr/bin/env python3
 """Benchmark of the exact Hamming kNN-graph build on one MI355X.
 
-One step = one ``bdg_build_knn_ex`` call over the whole workload: every
-(row block x column block) distance tile with its fused top-K, the merge of
-the per-column-block lists, and the output rows. Codes are resident in HBM
-before the timed region starts.
+One step = one ``bdg_build_knn_ex`` call over the whole workload: operand
+prep, every (row tile x column block) distance tile with its fused top-K, the
+running merge of the per-column-block lists, and the output rows. Codes are
+resident in HBM before the timed region starts.
 
-Default workload: 1,000,000 codes of 256 bits from 1,000 random centres with
-bit-flip probability 0.2, exact K = 64 graph, built in 131072 x 131072 blocks
-with merged per-block lists.
+Default workload: one GPU's partition at production shape -- 4,000,000 codes
+of 512 bits from 20,000 random centres with bit-flip probability 0.25, exact
+K = 100 graph (row blocks of 250,000, column blocks of 262,144). The vector-ALU
+path is timed beside it (one step by default), and the 1,000,000 x 256-bit,
+K = 64 workload is timed as a secondary object.
 
 Prints ONE JSON line on stdout. ``value`` = n (n - 1) / seconds per step
 (pair distances per second). ``roofline`` is for the dominant kernel (the
 distance tile), timed live with HIP events recorded around every tile launch on
-the launch stream. ``cpu_baseline`` times the CPU oracle on a bounded seeded
-row sample of the same workload.
+the launch stream. ``stall`` is the persistent launch's stall flag after the
+timed builds (``bdg_build_knn_check``; 0 in a correct run). ``cpu_baseline``
+times the CPU oracle on a bounded seeded row sample of the same workload, on
+all host threads and on one.
 
     python bench.py [--steps 5] [--warmup 2] [--path auto|mfma|popc]
+                    [--workload NAME] [--secondary NAME|none]
 """
 from __future__ import annotations
 
@@ -166,6 +171,13 @@ def run_path(codes_dev, n, bits, K, path, row_block, col_block, steps, warmup):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / steps
+    # outcome of the last build on this workspace: the persistent launch's
+    # stall flag (never set in a correct run)
+    chk = bdg.make_opts(path=path, row_block=row_block, col_block=col_block,
+                        workspace=ws.data_ptr(), workspace_bytes=ws_bytes)
+    stall = bdg.bdg_build_knn_check(n, bits, K, chk, stream)
+    if stall != 0:
+        raise RuntimeError(f"bdg_build_knn_check: {stall} {bdg.last_error()}")
     durs, pairs = [], []
     for s in range(steps):
         for i, (rows, cols) in enumerate(shapes):
@@ -176,7 +188,7 @@ def run_path(codes_dev, n, bits, K, path, row_block, col_block, steps, warmup):
     # pairs per launch x launches / total kernel time = pairs / (average duration)
     return ms_step, dict(launches=len(durs), avg_ms=float(np.mean(durs)),
                          pairs_per_launch=float(np.mean(pairs)),
-                         total_ms=float(np.sum(durs))), (idx, dist)
+                         total_ms=float(np.sum(durs)), stall=stall), (idx, dist)
 
 
 def cpu_baseline(codes, K, gpu_out, target_s):
@@ -197,11 +209,39 @@ def cpu_baseline(codes, K, gpu_out, target_s):
     t = time.perf_counter() - t0
     gi, gd = bdg.to_numpy_graph(*gpu_out)
     parity = bool(np.array_equal(gi[rows], oi) and np.array_equal(gd[rows], od))
-    return dict(value=R * (n - 1) / t, unit="pair-dist/s", cores=oracle.threads(),
+    cores = oracle.threads()
+    # the same oracle on one thread, on a share of the sample sized for about
+    # a third of the time budget
+    r1 = int(max(4, min(R, R * (target_s / 3) / max(t, 1e-3) / max(cores, 1))))
+    rows1 = rows[:r1]
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        o1i, o1d = oracle.knn_rows(codes, K, rows=rows1)
+        t1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(cores)
+    parity = parity and bool(np.array_equal(o1i, oi[:r1]) and np.array_equal(o1d, od[:r1]))
+    return dict(value=R * (n - 1) / t, unit="pair-dist/s", cores=cores,
                 kind="oracle", seconds=t,
                 sample=f"{R} seeded rows x all {n} columns of the same workload "
                        f"(exact K={K} rows by the C oracle)",
-                parity_on_sample=parity)
+                parity_on_sample=parity,
+                single_thread={"value": r1 * (n - 1) / t1, "seconds": t1,
+                               "sample": f"the first {r1} rows of the same sample"},
+                host={"cpu_model": cpu_model(), "affinity_cores": len(os.sched_getaffinity(0)),
+                      "oracle_build": "gcc -O2 -mpopcnt -fopenmp (portable x86-64 flags)"})
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def recall_leg():
@@ -484,6 +524,74 @@ def bench_batched(args, w):
     plan.close()
 
 
+def time_build(w, workload, path, steps, warmup, other_steps, other_warmup, other_path):
+    """Generate one single-partition workload, time its build on `path` (and
+    the other distance path for `other_steps`), return (codes, codes_dev,
+    outputs of the main path, result fields)."""
+    import torch
+    from paper_2102_04656_amd import bdg, datagen
+    n, bits, K = w["n"], w["bits"], w["K"]
+    row_block, col_block = w.get("row_block", 131072), w.get("col_block", 131072)
+    log(f"[bench] generating {workload}: n={n} bits={bits} K={K}")
+    t0 = time.perf_counter()
+    codes = datagen.clustered_codes(n, bits, w["n_centres"], w["p"], w["seed"])
+    log(f"[bench] generated in {time.perf_counter() - t0:.1f}s")
+    codes_dev = torch.from_numpy(codes.view(np.int64)).cuda()
+    torch.cuda.synchronize()
+
+    paths = {"mfma": bdg.PATH_MFMA, "popc": bdg.PATH_POPC}
+    runs, outs = {}, None
+    order = [path] + ([p for p in paths if p != path] if other_path else [])
+    for name in order:
+        st, wu = (steps, warmup) if name == path else (other_steps, other_warmup)
+        log(f"[bench] {workload}: timing path {name}: {st} steps after {wu} warmup")
+        ms, kern, out = run_path(codes_dev, n, bits, K, paths[name], row_block, col_block, st, wu)
+        runs[name] = dict(ms_per_step=ms, kernel=kern, steps=st)
+        if name == path:
+            outs = out
+        else:
+            del out
+        log(f"[bench] {name}: {ms:.2f} ms/step; tile kernel avg {kern['avg_ms']:.3f} ms "
+            f"x {kern['launches'] // st} launches/step")
+
+    pairs = n * (n - 1)
+
+    def roof(name):
+        kern = runs[name]["kernel"]
+        if name == "mfma":
+            ops_pair, peak, bound, kname = 2 * bits, PEAK_INT8_TOPS, "mfma", "knn_mfma_sweep_kernel"
+        else:
+            ops_pair, peak, bound, kname = 2 * bits // 32, PEAK_VALU_TOPS, "alu", "knn_popc_kernel"
+        achieved = kern["pairs_per_launch"] * ops_pair / (kern["avg_ms"] * 1e-3) / 1e12
+        r = {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TOP/s",
+             "frac": achieved / peak, "traffic": None, "kernel": kname,
+             "kernel_avg_ms": kern["avg_ms"], "ops_per_pair": ops_pair,
+             "pairs_per_launch": kern["pairs_per_launch"]}
+        rec = recorded_traffic(kname, workload)
+        if rec is not None:
+            r["traffic"] = rec["bytes_per_launch"]
+            r["traffic_source"] = (f"profiles/traffic__{kname}__{workload}.md (FETCH_SIZE + "
+                                   f"WRITE_SIZE per launch, copy-calibrated)")
+        return r
+
+    res = {"value": pairs / (runs[path]["ms_per_step"] * 1e-3),
+           "ms_per_step": runs[path]["ms_per_step"],
+           "dtype": "i8" if path == "mfma" else "u32",
+           "config": {"workload": workload, "n": n, "bits": bits, "K": K,
+                      "row_block": row_block, "col_block": col_block, "path": path,
+                      "centres": w["n_centres"], "flip_p": w["p"], "seed": w["seed"]},
+           "roofline": roof(path), "stall": runs[path]["kernel"]["stall"]}
+    for name, r in runs.items():
+        if name != path:
+            rr = roof(name)
+            res[f"{name}_path"] = {"value": pairs / (r["ms_per_step"] * 1e-3),
+                                   "ms_per_step": r["ms_per_step"], "steps": r["steps"],
+                                   "kernel_avg_ms": r["kernel"]["avg_ms"],
+                                   "achieved": rr["achieved"], "peak": rr["peak"],
+                                   "frac": rr["frac"], "stall": r["kernel"]["stall"]}
+    return codes, codes_dev, outs, res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__,
                                  formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -491,9 +599,15 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--path", choices=["auto", "mfma", "popc"], default="auto")
-    ap.add_argument("--workload", default="clustered-1m-256b-k64")
+    ap.add_argument("--workload", default="clustered-4m-512b-k100")
+    ap.add_argument("--secondary", default="clustered-1m-256b-k64",
+                    help="a second single-partition workload timed on the matrix-core path "
+                         "with the same steps (reported, not the value); 'none' to skip")
     ap.add_argument("--other-path", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the other distance path (reported, not the value)")
+    ap.add_argument("--other-steps", type=int, default=1,
+                    help="timed steps of the other distance path")
+    ap.add_argument("--other-warmup", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -522,84 +636,27 @@ def main():
     w = datagen.WORKLOADS[args.workload]
     if "n_shards" in w:
         return bench_batched(args, w)
-    n, bits, K = w["n"], w["bits"], w["K"]
-    row_block, col_block = w.get("row_block", 131072), w.get("col_block", 131072)
-    log(f"[bench] generating {args.workload}: n={n} bits={bits} K={K}")
-    t0 = time.perf_counter()
-    codes = datagen.clustered_codes(n, bits, w["n_centres"], w["p"], w["seed"])
-    log(f"[bench] generated in {time.perf_counter() - t0:.1f}s")
-    codes_dev = torch.from_numpy(codes.view(np.int64)).cuda()
-    torch.cuda.synchronize()
-
-    paths = {"mfma": bdg.PATH_MFMA, "popc": bdg.PATH_POPC}
     main_path = "mfma" if args.path == "auto" else args.path
-    runs = {}
-    order = [main_path] + ([p for p in paths if p != main_path] if args.other_path else [])
-    outs = None
-    for name in order:
-        log(f"[bench] timing path {name}: {args.steps} steps after {args.warmup} warmup")
-        ms, kern, out = run_path(codes_dev, n, bits, K, paths[name], row_block, col_block,
-                                 args.steps, args.warmup)
-        runs[name] = dict(ms_per_step=ms, kernel=kern)
-        if name == main_path:
-            outs = out
-        else:
-            del out
-        log(f"[bench] {name}: {ms:.2f} ms/step; tile kernel avg {kern['avg_ms']:.3f} ms "
-            f"x {kern['launches'] // args.steps} launches/step")
-
-    pairs = n * (n - 1)
-    ms = runs[main_path]["ms_per_step"]
-    kern = runs[main_path]["kernel"]
-    if main_path == "mfma":
-        ops_pair, peak, bound = 2 * bits, PEAK_INT8_TOPS, "mfma"
-    else:
-        ops_pair, peak, bound = 2 * bits // 32, PEAK_VALU_TOPS, "alu"
-    achieved = kern["pairs_per_launch"] * ops_pair / (kern["avg_ms"] * 1e-3) / 1e12
-    kname = "knn_mfma_sweep_kernel" if main_path == "mfma" else "knn_popc_kernel"
+    codes, codes_dev, outs, res = time_build(w, args.workload, main_path, args.steps, args.warmup,
+                                             args.other_steps, args.other_warmup, args.other_path)
+    n, bits, K = w["n"], w["bits"], w["K"]
     result = {
         "metric": METRIC,
-        "value": pairs / (ms * 1e-3),
+        "value": res.pop("value"),
         "unit": "pair-dist/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": res.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "i8" if main_path == "mfma" else "u32",
+        "dtype": res.pop("dtype"),
         "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "bits": bits, "K": K,
-                   "row_block": row_block, "col_block": col_block, "path": main_path,
-                   "centres": w["n_centres"], "flip_p": w["p"], "seed": w["seed"]},
-        "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TOP/s",
-                     "frac": achieved / peak, "traffic": None,
-                     "kernel": kname,
-                     "kernel_avg_ms": kern["avg_ms"],
-                     "ops_per_pair": ops_pair,
-                     "pairs_per_launch": kern["pairs_per_launch"]},
     }
-    rec = recorded_traffic(kname, args.workload)
-    if rec is not None:
-        result["roofline"]["traffic"] = rec["bytes_per_launch"]
-        result["roofline"]["traffic_source"] = (
-            f"profiles/traffic__{kname}__{args.workload}.md (FETCH_SIZE + WRITE_SIZE per launch, "
-            f"copy-calibrated)")
+    result.update(res)
     if args.copy_calibration:
         copy_calibration()
-    for name, r in runs.items():
-        if name == main_path:
-            continue
-        if name == "mfma":
-            o2, p2 = 2 * bits, PEAK_INT8_TOPS
-        else:
-            o2, p2 = 2 * bits // 32, PEAK_VALU_TOPS
-        a2 = r["kernel"]["pairs_per_launch"] * o2 / (r["kernel"]["avg_ms"] * 1e-3) / 1e12
-        result[f"{name}_path"] = {"value": pairs / (r["ms_per_step"] * 1e-3),
-                                  "ms_per_step": r["ms_per_step"],
-                                  "kernel_avg_ms": r["kernel"]["avg_ms"],
-                                  "achieved": a2, "peak": p2, "frac": a2 / p2}
     if not args.no_cpu_baseline:
         log(f"[bench] CPU oracle baseline (~{args.cpu_seconds:.0f}s sample)")
         result["cpu_baseline"] = cpu_baseline(codes, K, outs, args.cpu_seconds)
@@ -622,8 +679,15 @@ def main():
         log(f"[bench] dac: kmeans {d['kmeans_ms']:.1f} ms, graph {d['dac_ms']:.1f} ms (recall "
             f"{d['recall_dac']:.3f}), + propagation {d['propagate_ms']:.1f} ms (recall "
             f"{d['recall_dac_propagated']:.3f})")
+    del outs, codes_dev, codes
+    torch.cuda.empty_cache()
+    if args.secondary != "none" and args.secondary != args.workload:
+        w2 = datagen.WORKLOADS[args.secondary]
+        _, _, o2, r2 = time_build(w2, args.secondary, "mfma", args.steps, args.warmup, 0, 0,
+                                  other_path=False)
+        del o2
+        result["secondary"] = r2
     if args.recall:
-        del outs, codes_dev
         result["recall"] = recall_leg()
     print(json.dumps(result), flush=True)
 

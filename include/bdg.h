@@ -86,7 +86,12 @@ typedef struct bdg_knn_opts {
                                 [2i] and [2i + 1] are recorded on the stream
                                 just before and just after it, while
                                 2i + 1 < n_tile_events */
-    uint32_t reserved[4];
+    uint32_t wait_limit;     /* matrix-core path: polls one dependency wait of
+                                the persistent launch makes before it gives up
+                                and sets the stall flag (0 = default, seconds;
+                                a correct run never reaches it). Lowering it
+                                is a test hook for the give-up path */
+    uint32_t reserved[3];
 } bdg_knn_opts;
 
 /* ---------------------------------------------------------------- build --- */
@@ -122,6 +127,19 @@ int bdg_build_knn_ex(const uint64_t *codes, uint32_t n, uint32_t bits, uint32_t 
 /* Workspace bytes bdg_build_knn_ex needs for these arguments (0 if none). */
 int bdg_build_knn_workspace_size(uint32_t n, uint32_t bits, uint32_t K,
                                  const bdg_knn_opts *opts, size_t *bytes);
+
+/*
+ * Outcome of the last bdg_build_knn_ex enqueued with this caller workspace
+ * (opts->workspace) and the same n, bits, K and opts: waits for `stream`,
+ * then reads the persistent launch's stall flag from the workspace's control
+ * words. BDG_OK if the build completed normally (or its path has no
+ * persistent launch), BDG_EDEVICE if a dependency wait gave up (the lists
+ * are then unspecified; never in a correct run), BDG_EINVAL for a NULL or too
+ * small workspace. The workspace is only read. The async build has no other
+ * way to report this: its return value is decided before the kernel runs.
+ */
+int bdg_build_knn_check(uint32_t n, uint32_t bits, uint32_t K, const bdg_knn_opts *opts,
+                        void *stream);
 
 /*
  * Merge neighbour lists (Sec. 3.2 second reduce; Sec. 3.3 merge-sort).
@@ -268,7 +286,10 @@ int bdg_batch_plan_create(const uint64_t *offsets, uint32_t S, uint32_t bits, ui
                           const bdg_knn_opts *opts, bdg_batch_plan **plan);
 void bdg_batch_plan_destroy(bdg_batch_plan *plan);
 int bdg_batch_plan_info(const bdg_batch_plan *plan, bdg_batch_info *info);
-/* Change the work order (re-uploads the work list; drops a captured graph). */
+/* Change the work order (re-uploads the work list; drops a captured graph).
+ * Waits for all work queued on the device first, so a launch of the plan
+ * still in flight on any stream finishes with the old list. A plan holds one
+ * work counter: its launches must not overlap (enqueue them on one stream). */
 int bdg_batch_plan_set_order(bdg_batch_plan *plan, int order);
 
 /* Enqueue the build of every shard on `stream` (operand prep, counter reset,

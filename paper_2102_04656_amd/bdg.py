@@ -50,7 +50,8 @@ class KnnOpts(ctypes.Structure):
         ("tile_variant", ctypes.c_uint32),
         ("n_tile_events", ctypes.c_uint32),
         ("tile_events", ctypes.c_void_p),
-        ("reserved", ctypes.c_uint32 * 4),
+        ("wait_limit", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 3),
     ]
 
 
@@ -112,6 +113,7 @@ _SIGS = {
     "bdg_build_knn": [_p, _u32, _u32, _u32, _p, _p],
     "bdg_build_knn_ex": [_p, _u32, _u32, _u32, _p, _p, _p, _p],
     "bdg_build_knn_workspace_size": [_u32, _u32, _u32, _p, _p],
+    "bdg_build_knn_check": [_u32, _u32, _u32, _p, _p],
     "bdg_merge_lists": [_p, _p, _u32, _u32, _u32, _u32, _p, _p, _p],
     "bdg_propagate": [_p, _u32, _u32, _u32, _p, _p, _p, _p],
     "bdg_bkmeans": [_p, _u32, _u32, _p, _u32, _p, _u32, _u32, _p, _p],
@@ -203,6 +205,13 @@ def bdg_build_knn_ex(codes, n, bits, K, out_idx, out_dist, opts=None, stream=Non
     op = ctypes.byref(opts) if opts is not None else None
     return lib().bdg_build_knn_ex(_ptr(codes), n, bits, K, _ptr(out_idx), _ptr(out_dist), op,
                                   _stream(stream))
+
+
+def bdg_build_knn_check(n, bits, K, opts, stream=None) -> int:
+    """Status of the last build enqueued with this caller workspace (waits
+    for the stream): 0, or BDG_EDEVICE if the persistent launch's stall flag
+    is set."""
+    return lib().bdg_build_knn_check(n, bits, K, ctypes.byref(opts), _stream(stream))
 
 
 def bdg_build_knn_workspace_size(n, bits, K, opts=None) -> int:

@@ -90,8 +90,14 @@ int upload_items(bdg_batch_plan* p) {
       make_items(p->offsets, bdg::run_rows_per_wg(p->K), p->order);
   if (items.size() != p->nitems) return bdg::api_error(BDG_EDEVICE, "work item count changed");
   if (p->nitems) {
-    hipError_t e = hipMemcpy(p->items, items.data(), items.size() * sizeof(bdg::BatchItem),
-                             hipMemcpyHostToDevice);
+    // A launch of this plan may still be in flight on any stream (a pool
+    // stream does not wait for the null stream): let every queued launch
+    // finish before its work list is rewritten. This is a set-up call, never
+    // on the build path.
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess)
+      e = hipMemcpy(p->items, items.data(), items.size() * sizeof(bdg::BatchItem),
+                    hipMemcpyHostToDevice);
     if (e != hipSuccess) return bdg::api_device_error(e, "work item upload");
   }
   drop_graph(p);

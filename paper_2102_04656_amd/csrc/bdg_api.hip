@@ -239,6 +239,7 @@ int bdg_build_knn_ex(const uint64_t* codes, uint32_t n, uint32_t bits, uint32_t 
       a.grid = (uint32_t)(cus > 0 ? cus : 1);
       a.out_idx = out_idx + (size_t)r0 * K;
       a.out_dist = out_dist + (size_t)r0 * K;
+      a.spin_limit = (opts && opts->struct_size >= sizeof(bdg_knn_opts)) ? opts->wait_limit : 0;
       const bool timed = opts && opts->tile_events && opts->n_tile_events >= 2;
       if (timed) e = hipEventRecord(reinterpret_cast<hipEvent_t>(opts->tile_events[0]), stream);
       if (e == hipSuccess) e = bdg::launch_mfma_sweep(a, stream);
@@ -293,6 +294,31 @@ int bdg_build_knn_ex(const uint64_t* codes, uint32_t n, uint32_t bits, uint32_t 
   return result;
 }
 
+int bdg_build_knn_check(uint32_t n, uint32_t bits, uint32_t K, const bdg_knn_opts* opts,
+                        void* stream) {
+  g_last_error.clear();
+  Plan p;
+  int st = make_plan(n, bits, K, opts, &p);
+  if (st != BDG_OK) return st;
+  if (!p.running || n == 0) return BDG_OK;  // no persistent launch, no flag
+  if (!opts || !opts->workspace) return set_error(BDG_EINVAL, "opts->workspace is NULL");
+  if (opts->workspace_bytes < p.ws_bytes)
+    return set_error(BDG_EINVAL, "workspace too small: %zu < %zu bytes", opts->workspace_bytes,
+                     p.ws_bytes);
+  (void)hipGetLastError();
+  hipError_t e = hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_error(e, "synchronize");
+  uint32_t stall = 0;
+  e = hipMemcpy(&stall,
+                static_cast<const char*>(opts->workspace) + p.ws_ctl_off + 4 * bdg::kSweepStallWord,
+                sizeof stall, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return device_error(e, "stall flag read");
+  if (stall)
+    return set_error(BDG_EDEVICE,
+                     "a dependency wait of the persistent build ran out; lists unspecified");
+  return BDG_OK;
+}
+
 int bdg_build_knn(const uint64_t* codes, uint32_t n, uint32_t bits, uint32_t K, uint32_t* out_idx,
                   uint16_t* out_dist) {
   g_last_error.clear();
@@ -318,22 +344,7 @@ int bdg_build_knn(const uint64_t* codes, uint32_t n, uint32_t bits, uint32_t K, 
   o.workspace = ws;
   o.workspace_bytes = p.ws_bytes;
   st = bdg_build_knn_ex(codes, n, bits, K, out_idx, out_dist, &o, nullptr);
-  if (st == BDG_OK) {
-    hipError_t e = hipStreamSynchronize(nullptr);
-    if (e != hipSuccess) {
-      st = device_error(e, "synchronize");
-    } else if (p.running) {
-      uint32_t stall = 0;
-      e = hipMemcpy(&stall,
-                    static_cast<char*>(ws) + p.ws_ctl_off + 4 * bdg::kSweepStallWord,
-                    sizeof stall, hipMemcpyDeviceToHost);
-      if (e != hipSuccess)
-        st = device_error(e, "stall flag read");
-      else if (stall)
-        st = set_error(BDG_EDEVICE,
-                       "a dependency wait of the persistent build ran out; lists unspecified");
-    }
-  }
+  if (st == BDG_OK) st = bdg_build_knn_check(n, bits, K, &o, nullptr);
   if (ws) (void)hipFree(ws);
   return st;
 }

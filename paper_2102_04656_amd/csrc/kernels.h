@@ -134,6 +134,7 @@ struct SweepArgs {
   uint32_t grid;  // persistent work-groups
   uint32_t* out_idx;
   uint16_t* out_dist;
+  uint32_t spin_limit = 0;  // polls of one dependency wait before it gives up (0: default)
 };
 constexpr uint32_t kSweepStallWord = 1;  // ctl[1] != 0: a dependency wait ran out
 size_t sweep_ctl_words(uint32_t nrows, uint32_t K);

@@ -635,9 +635,11 @@ __global__ __launch_bounds__(threads_of(W, NR), 1) void knn_mfma_batched_kernel(
   }
 }
 
-// Bound on the polls of one dependency wait (each polls, then sleeps about
-// 1,000 cycles): seconds, far beyond any item. The wait order makes the bound
-// unreachable; it only guarantees that every wave exits.
+// Default bound on the polls of one dependency wait (each polls, then sleeps
+// about 1,000 cycles): seconds, far beyond any item. The wait order makes the
+// bound unreachable; it only guarantees that every wave exits. A caller can
+// set a lower bound (a test forces the give-up path that way: every wave
+// still exits normally and the stall flag is set).
 constexpr uint32_t kSweepSpinLimit = 1u << 23;
 
 // A whole build in one persistent launch (SweepArgs): every work-group takes
@@ -654,7 +656,7 @@ __global__ __launch_bounds__(threads_of(W, NR), 1) void knn_mfma_sweep_kernel(
     const v4i* __restrict__ frags, const uint64_t* __restrict__ codes, uint32_t K, uint32_t bits,
     uint32_t IB, uint32_t row0, uint32_t nrows, uint32_t ncols, uint32_t col_block,
     uint32_t ntiles, uint32_t nitems, uint32_t* ctl, uint32_t* __restrict__ out_idx,
-    uint16_t* __restrict__ out_dist) {
+    uint16_t* __restrict__ out_dist, uint32_t spin_limit) {
   __shared__ TileRing<GPS * W * 64, NST> ring;
   __shared__ uint32_t cur;
   extern __shared__ uint32_t state[];
@@ -671,7 +673,7 @@ __global__ __launch_bounds__(threads_of(W, NR), 1) void knn_mfma_sweep_kernel(
       if (threadIdx.x == 0) {
         for (uint32_t spins = 0; __hip_atomic_load(&progress[t], __ATOMIC_ACQUIRE,
                                                    __HIP_MEMORY_SCOPE_AGENT) < c;) {
-          if (++spins == kSweepSpinLimit) {
+          if (++spins >= spin_limit) {
             __hip_atomic_store(&ctl[kSweepStallWord], 1u, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
             break;
@@ -801,7 +803,7 @@ inline hipError_t launch_sweep_w(const SweepArgs& a, hipStream_t stream) {
   hipLaunchKernelGGL(kern, dim3(grid), dim3(threads_of(W, NR)), lds, stream,
                      reinterpret_cast<const v4i*>(a.frags), a.codes, a.K, a.bits, a.idx_bits,
                      a.row0, a.nrows, a.ncols, a.col_block, ntiles, nitems, a.ctl, a.out_idx,
-                     a.out_dist);
+                     a.out_dist, a.spin_limit ? a.spin_limit : kSweepSpinLimit);
   return hipGetLastError();
 }
 

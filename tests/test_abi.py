@@ -133,3 +133,19 @@ def test_merge_rejects_bad_arguments():
     assert L.bdg_merge_lists(FAKE, FAKE, 10, 2, 4, 300, FAKE, FAKE, None) == bdg.BDG_EUNSUPPORTED
     assert L.bdg_merge_lists(None, FAKE, 10, 2, 4, 4, FAKE, FAKE, None) == bdg.BDG_EINVAL
     assert L.bdg_merge_lists(None, None, 0, 2, 4, 4, None, None, None) == bdg.BDG_OK
+
+
+def test_build_check_validates_before_touching_the_gpu():
+    L = bdg.lib()
+    # matrix-core path: the flag lives in the caller's workspace
+    o = bdg.make_opts(path=bdg.PATH_MFMA, col_block=64)
+    assert L.bdg_build_knn_check(1000, 256, 16, ctypes.byref(o), None) == bdg.BDG_EINVAL
+    need = bdg.bdg_build_knn_workspace_size(1000, 256, 16, o)
+    o.workspace, o.workspace_bytes = 0x1000, need - 1
+    assert L.bdg_build_knn_check(1000, 256, 16, ctypes.byref(o), None) == bdg.BDG_EINVAL
+    assert "too small" in bdg.last_error()
+    assert L.bdg_build_knn_check(1000, 100, 16, ctypes.byref(o), None) == bdg.BDG_EINVAL
+    # no persistent launch on the vector-ALU path, nothing to read; n = 0 too
+    o = bdg.make_opts(path=bdg.PATH_POPC)
+    assert L.bdg_build_knn_check(1000, 256, 16, ctypes.byref(o), None) == bdg.BDG_OK
+    assert L.bdg_build_knn_check(0, 256, 16, None, None) == bdg.BDG_OK
