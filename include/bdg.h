@@ -142,6 +142,27 @@ int bdg_build_knn_check(uint32_t n, uint32_t bits, uint32_t K, const bdg_knn_opt
                         void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * matrix-core build of bdg_build_knn_ex (default blocks) with its workspace
+ * in a static device array of BDG_NOALLOC_SCRATCH_MB MiB inside the library,
+ * one copy per device, held until the process ends. The call allocates
+ * nothing; the caller still passes codes and outputs (device pointers, as
+ * bdg_build_knn_ex) and the stream, on which the work is enqueued.
+ * Limit: the build's workspace (bdg_build_knn_workspace_size with path MFMA:
+ * about n x bits bytes of operand fragments plus control words) must fit,
+ * e.g. n up to about 260,000 codes of 256 bits or 130,000 of 512 bits; larger
+ * inputs return BDG_EUNSUPPORTED before anything is enqueued. Every call on a
+ * device shares that device's array: calls that overlap on one device (two
+ * streams, two threads) race and must be serialised by the caller. Errors as
+ * bdg_build_knn_ex; the stall flag can be read with bdg_build_knn_check only
+ * through a caller workspace, so this variant does not report it.
+ */
+#define BDG_NOALLOC_SCRATCH_MB 64
+int bdg_build_knn_noalloc(const uint64_t *codes, uint32_t n, uint32_t bits, uint32_t K,
+                          uint32_t *out_idx, uint16_t *out_dist, void *stream);
+
+/*
  * Merge neighbour lists (Sec. 3.2 second reduce; Sec. 3.3 merge-sort).
  *   in_idx/in_dist  [L][n][K_in], each list sorted by (dist, idx) and possibly
  *                   padded with sentinels (BDG_NO_IDX, BDG_NO_DIST)

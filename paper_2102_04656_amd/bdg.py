@@ -114,6 +114,7 @@ _SIGS = {
     "bdg_build_knn_ex": [_p, _u32, _u32, _u32, _p, _p, _p, _p],
     "bdg_build_knn_workspace_size": [_u32, _u32, _u32, _p, _p],
     "bdg_build_knn_check": [_u32, _u32, _u32, _p, _p],
+    "bdg_build_knn_noalloc": [_p, _u32, _u32, _u32, _p, _p, _p],
     "bdg_merge_lists": [_p, _p, _u32, _u32, _u32, _u32, _p, _p, _p],
     "bdg_propagate": [_p, _u32, _u32, _u32, _p, _p, _p, _p],
     "bdg_bkmeans": [_p, _u32, _u32, _p, _u32, _p, _u32, _u32, _p, _p],
@@ -212,6 +213,13 @@ def bdg_build_knn_check(n, bits, K, opts, stream=None) -> int:
     for the stream): 0, or BDG_EDEVICE if the persistent launch's stall flag
     is set."""
     return lib().bdg_build_knn_check(n, bits, K, ctypes.byref(opts), _stream(stream))
+
+
+def bdg_build_knn_noalloc(codes, n, bits, K, out_idx, out_dist, stream=None) -> int:
+    """The matrix-core build with the library's static workspace (allocates
+    nothing; inputs up to the static scratch size)."""
+    return lib().bdg_build_knn_noalloc(_ptr(codes), n, bits, K, _ptr(out_idx), _ptr(out_dist),
+                                       _stream(stream))
 
 
 def bdg_build_knn_workspace_size(n, bits, K, opts=None) -> int:
