@@ -127,11 +127,12 @@ template <int NR>
 __device__ __forceinline__ int flush_sub(uint32_t* list_q, const uint32_t* buf_q,
                                          uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                          uint32_t K, uint32_t lane, uint32_t IB, uint32_t bits) {
-  static_assert(kBuf == 32, "the pending keys of a query fill lanes 32..63");
+  static_assert(kBuf <= 32 && kBuf % 4 == 0, "the pending keys of a query fit lanes 32..63");
   const uint32_t b = lane - 32u;  // slot of lane 32 + b
-  const uint32_t t = b >> 3;
+  const uint32_t t = b / kSub;
   const uint32_t ct = t == 0 ? c0 : (t == 1 ? c1 : (t == 2 ? c2 : c3));
-  const uint32_t x = (lane >= 32u && (b & (kSub - 1)) < ct) ? buf_q[b] : kKeyNone;
+  const uint32_t x =
+      (lane >= 32u && b < (uint32_t)kBuf && b % kSub < ct) ? buf_q[b] : kKeyNone;
   uint32_t R[NR];
   load_list<NR>(list_q, R, K, lane);  // in flight together with the pending keys
   const uint32_t kth = merge_desc_with<NR>(list_q, R, wave_sort_upper32_desc(x, lane), K, lane);
@@ -416,7 +417,10 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
           acc[u][gq] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[u][s], bq[gq][s],
                                                              s == 0 ? biasC[gq] : acc[u][gq], 0, 0, 0);
       work(s);
-      __builtin_amdgcn_sched_barrier(0);
+      // without a producer, a fence per layer keeps each operand read after
+      // the products that free its registers; with one, the compiler's own
+      // schedule of the reads was measured faster
+      if constexpr (!PROD) __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int gq = 0; gq < QG; ++gq) bb[gq] = biasC[gq][0] + (int)bits;
@@ -426,23 +430,104 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
     for (int u = 0; u < U; ++u) append(acc[u], bb, cs + 16 * u);
   };
 
-  // Per stage: the contraction of unit j is issued before the filter of unit
-  // j - 1 (ping-pong accumulators), so the matrix cores keep busy while the
+  // Units are contracted in a ping-pong of accumulators: unit j is issued
+  // before the filter of unit j - 1, so the matrix cores keep busy while the
   // vector ALUs test. A unit contracted before a merge tightened a threshold
   // just admits a superset; its keys use the bias it was contracted with. The
   // max-reduction of unit j - 1 is spread over the layers of unit j's
   // contraction (tile u QG + gq in layer (u QG + gq) % W), and so are the
-  // operand reads of unit j + 1 of the same stage: layer s of unit j + 1 is
-  // read into the registers layer s of unit j has just consumed, a whole
-  // unit ahead of its use.
+  // operand reads of unit j + 1: layer s of unit j + 1 is read into the
+  // registers layer s of unit j has just consumed, a whole unit ahead of its
+  // use.
   v4i acc[2][U][QG];
   int bb[2][QG];
+  if constexpr (PROD) {
+    // With a producer the unit stream runs across stage boundaries: the last
+    // unit of stage st filters nothing new and reads the first unit of stage
+    // st + 1 once that stage is known to have landed (a count read one unit
+    // earlier, so the read never waits), and the first unit of a stage
+    // filters the last unit of the previous one. The matrix cores then see no
+    // gap at a stage start, except when the producer has fallen behind.
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int gq = 0; gq < QG; ++gq) acc[1][u][gq] = v4i{0, 0, 0, 0};  // nothing passes
+#pragma unroll
+    for (int gq = 0; gq < QG; ++gq) bb[1][gq] = 0;
+    uint32_t avail = 0;  // stages known to have landed
+    bool have = false;   // `a` already holds the operands of the stage's first unit
+    v4i a[U][W];         // operands of the unit being contracted (then of the next)
+    uint32_t slot = 0;   // st % NST
+#pragma unroll 1
+    for (uint32_t st = 0; st < nst; ++st) {
+      const uint32_t nslot = slot + 1 == (uint32_t)NST ? 0u : slot + 1;
+      const v4i* sb = stage[slot];
+      const uint32_t cs0 = cstart + st * CT;
+      if (!have) {
+        while (st >= avail) {
+          avail = __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+              &ring.published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+          if (st >= avail) __builtin_amdgcn_s_sleep(1);
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int s = 0; s < W; ++s) a[u][s] = sb[(u * W + s) * 64 + lane];
+      }
+      // landed count, read now and looked at in the stage's last unit
+      const uint32_t pubv = __hip_atomic_load(&ring.published, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_WORKGROUP);
+      bool pf = false;  // the next stage's first unit is read during the last unit
+#pragma unroll
+      for (int j = 0; j < NU; ++j) {
+        const v4i* nb = sb + (U * (j + 1)) * W * 64;  // operands of unit j + 1
+        if (j + 1 == NU) {
+          // every operand of the stage is in registers or on its way (this
+          // wave's LDS reads complete in order, before the count below): the
+          // slot can be reused
+          // (every lane stores the same count: no lane mask to set up)
+          __atomic_signal_fence(__ATOMIC_SEQ_CST);
+          __hip_atomic_store(&ring.done[wave], st + 1, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+          const uint32_t seen = __builtin_amdgcn_readfirstlane(pubv);
+          avail = seen > avail ? seen : avail;
+          pf = st + 1 < nst && st + 1 < avail;
+          nb = stage[nslot];
+          __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        v4i (&accP)[U][QG] = acc[(j + 1) & 1];  // the previous unit (stage st - 1's last for j = 0)
+        int mx = accP[0][0][0];
+        issue_with(acc[j & 1], bb[j & 1], a, [&](int s) {
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int gq = 0; gq < QG; ++gq)
+              if ((u * QG + gq) % W == s)
+                mx = max(mx, max(max(accP[u][gq][0], accP[u][gq][1]),
+                                 max(accP[u][gq][2], accP[u][gq][3])));
+          // (in the last unit these reads are made whether or not the next
+          // stage has landed: reading a slot never disturbs the producer,
+          // and operands read too early are read again at the stage start)
+#pragma unroll
+          for (int u = 0; u < U; ++u) a[u][s] = nb[(u * W + s) * 64 + lane];
+        });
+        if (__any(mx > 0))
+          append_unit(accP, bb[(j + 1) & 1], cs0 + 16 * U * j - 16 * U);
+      }
+      have = pf;
+      slot = nslot;
+    }
+    if (nst > 0) {
+      if (__any(maxacc(acc[1]) > 0)) append_unit(acc[1], bb[1], cstart + nst * CT - 16 * U);
+    }
+  } else {
   uint32_t pend = 0xFFFFFFFFu;  // stage this wave copies and has not published
-  uint32_t avail = 0;           // with a producer: stages known to have landed
 #pragma unroll 1
   for (uint32_t st = 0; st < nst; ++st) {
     const uint32_t slot = st % NST;
-    if (!PROD && pend != 0xFFFFFFFFu) {  // publish the copy issued one stage ago
+    if (pend != 0xFFFFFFFFu) {  // publish the copy issued one stage ago
       BDG_WAIT_VMCNT(0);
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
       if (lane == 0)
@@ -450,23 +535,13 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
                            __HIP_MEMORY_SCOPE_WORKGROUP);
       pend = 0xFFFFFFFFu;
     }
-    if constexpr (PROD) {
-      // The producer runs ahead: the count of landed stages is re-read only
-      // when this wave has caught up with the last value it saw.
-      while (st >= avail) {
-        avail = __builtin_amdgcn_readfirstlane(__hip_atomic_load(
-            &ring.published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
-        if (st >= avail) __builtin_amdgcn_s_sleep(1);
-      }
-    } else {
-      while (__hip_atomic_load(&ring_landed[slot], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_WORKGROUP) < st / NST + 1)
-        __builtin_amdgcn_s_sleep(1);
-    }
+    while (__hip_atomic_load(&ring_landed[slot], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP) < st / NST + 1)
+      __builtin_amdgcn_s_sleep(1);
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     const uint32_t t = st + NST - 1;
-    if (!PROD && t < nst && __hip_atomic_load(&ring_claimed, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_WORKGROUP) == t) {
+    if (t < nst && __hip_atomic_load(&ring_claimed, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_WORKGROUP) == t) {
       uint32_t won = 0;
       if (lane == 0) {
         uint32_t expect = t;
@@ -538,6 +613,7 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
   }
   if (NU % 2 == 0 && nst > 0) {
     if (__any(maxacc(acc[1]) > 0)) append_unit(acc[1], bb[1], cstart + nst * CT - 16 * U);
+  }
   }
   BDG_WAIT_VMCNT(0);  // no stage copy of this wave is still in flight
 
