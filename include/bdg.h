@@ -55,8 +55,9 @@ typedef enum bdg_status {
 } bdg_status;
 
 /* Which distance tile computes the Hamming distances. Both give identical
- * graphs: XOR + popcount on the vector ALUs, or an exact +-1 int8 matrix-core
- * contraction with ham = popcount(q) - <a, 2q - 1>. */
+ * graphs: XOR + popcount on the vector ALUs, or an exact int8 matrix-core
+ * contraction of {0, 1} candidate bytes a with +-1 query bytes 2q - 1, with
+ * ham = popcount(q) - <a, 2q - 1>. */
 typedef enum bdg_path {
     BDG_PATH_AUTO = 0,
     BDG_PATH_POPC = 1,

@@ -93,7 +93,7 @@ struct RunArgs {
 uint32_t run_idx_bits(uint32_t bits);
 bool run_supported(uint32_t n, uint32_t words, uint32_t K);
 uint32_t run_rows_per_wg(uint32_t K);
-// Operand prep: +-1 int8 fragments of every code, prep_bytes(n, words) bytes.
+// Operand prep: {0, 1} int8 fragments of every code, prep_bytes(n, words) bytes.
 size_t prep_bytes(uint32_t n, uint32_t words);
 hipError_t launch_prep(const uint64_t* codes, uint32_t n, uint32_t words, void* frags,
                        hipStream_t stream);

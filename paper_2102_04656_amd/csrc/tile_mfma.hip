@@ -4,12 +4,16 @@
 // The first reduce of the single-pass divide-and-conquer searches every record
 // of a partition against all its records exhaustively (Sec. 3.2); the paper
 // moved those distance computations to native code (Sec. 3.6 (2)). Here the
-// distances are an int8 contraction: with s = 2y - 1 in {-1, +1}^b,
-//   <s_a, s_q> = b - 2 ham(a, q),
-// exact in int32, so ham = (b - dot) / 2 (on {0,1} vectors the squared
-// Euclidean distance of Eq. 1 is the same Hamming distance).
+// distances are an int8 contraction of a query q as s = 2q - 1 in {-1, +1}^b
+// against a candidate a as its {0, 1} bits:
+//   <s, a> = popc(q & a) - popc(~q & a) = popc(q) - ham(q, a),
+// exact in int32, so ham = popc(q) - dot (on {0,1} vectors the squared
+// Euclidean distance of Eq. 1 is the same Hamming distance). Candidates as
+// {0, 1} bytes rather than +-1 bytes toggle far fewer bits of the multipliers:
+// a throughput probe with random operands sustained 98 % of the int8 peak
+// with {0, 1} x +-1 bytes against 88 % with +-1 x +-1.
 //
-// Operands. A one-off prep kernel writes every code as +-1 bytes in the
+// Operands. A one-off prep kernel writes every code as {0, 1} bytes in the
 // operand order of v_mfma_i32_16x16x64_i8: per group of 16 codes and per
 // 64-bit word s, a 1 KB fragment whose lane l holds the 16 bytes of code
 // (16 g + l % 16), bits [64 s + 16 (l / 16), +16). Loading a fragment is one
@@ -29,8 +33,8 @@
 // the stages and publishes a count of landed ones; otherwise the compute waves
 // claim and copy stages themselves.
 //
-// Filter. The accumulator starts at the per-query bias 2 thr - b, so after
-// the contraction acc = 2 (thr - ham): a candidate can enter the list only if
+// Filter. The accumulator starts at the per-query bias thr - popc(q), so after
+// the contraction acc = thr - ham: a candidate can enter the list only if
 // acc > 0. The common case (no candidate of a 16-code group beats any of the
 // wave's thresholds) costs a max-reduction and one compare per group.
 //
@@ -54,7 +58,7 @@ namespace mfma {
 
 // One thread per 16-byte operand chunk; rows >= n are zero (a zero operand
 // gives dot 0; such columns are never admitted by the column-range test).
-__global__ __launch_bounds__(256) void prep_pm1_kernel(const uint64_t* __restrict__ codes,
+__global__ __launch_bounds__(256) void prep_01_kernel(const uint64_t* __restrict__ codes,
                                                        uint32_t n, uint32_t W, size_t chunks,
                                                        v4i* __restrict__ frags) {
   const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
@@ -64,7 +68,7 @@ __global__ __launch_bounds__(256) void prep_pm1_kernel(const uint64_t* __restric
   const uint32_t s = (uint32_t)(f % W);
   const size_t row = (f / W) * 16 + (l & 15u);
   v4i v = {0, 0, 0, 0};
-  if (row < n) v = code_chunk_pm1(codes, W, (uint32_t)row, s, l >> 4);
+  if (row < n) v = code_chunk_01(codes, W, (uint32_t)row, s, l >> 4);
   frags[t] = v;
 }
 
@@ -92,7 +96,7 @@ hipError_t launch_prep(const uint64_t* codes, uint32_t n, uint32_t words, void* 
                        hipStream_t stream) {
   const size_t chunks = prep_rows(n) * words * 4;
   dim3 grid((unsigned)((chunks + 255) / 256));
-  hipLaunchKernelGGL(mfma::prep_pm1_kernel, grid, dim3(256), 0, stream, codes, n, words, chunks,
+  hipLaunchKernelGGL(mfma::prep_01_kernel, grid, dim3(256), 0, stream, codes, n, words, chunks,
                      reinterpret_cast<mfma::v4i*>(frags));
   return hipGetLastError();
 }

@@ -27,6 +27,14 @@ __device__ __forceinline__ uint32_t spread_nibble(uint32_t nib) {
   return (nib * 0x00204081u) & 0x01010101u;
 }
 
+// 16 code bits -> 16 bytes of {0, 1} (0x01 for a set bit, 0x00 for a clear one).
+__device__ __forceinline__ v4i expand_01(uint32_t h) {
+  v4i r;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) r[t] = (int)spread_nibble((h >> (4 * t)) & 15u);
+  return r;
+}
+
 // 16 code bits -> 16 bytes of +-1 (0x01 for a set bit, 0xFF for a clear one).
 __device__ __forceinline__ v4i expand_pm1(uint32_t h) {
   v4i r;
@@ -36,11 +44,17 @@ __device__ __forceinline__ v4i expand_pm1(uint32_t h) {
   return r;
 }
 
-// Operand bytes of code `row`, word s, lane quarter kq.
+// Operand bytes of code `row`, word s, lane quarter kq: +-1 (the queries) or
+// {0, 1} (the candidate fragments).
 __device__ __forceinline__ v4i code_chunk_pm1(const uint64_t* codes, uint32_t W, uint32_t row,
                                               uint32_t s, uint32_t kq) {
   const uint64_t w = codes[(size_t)row * W + s];
   return expand_pm1((uint32_t)(w >> (16 * kq)) & 0xFFFFu);
+}
+__device__ __forceinline__ v4i code_chunk_01(const uint64_t* codes, uint32_t W, uint32_t row,
+                                             uint32_t s, uint32_t kq) {
+  const uint64_t w = codes[(size_t)row * W + s];
+  return expand_01((uint32_t)(w >> (16 * kq)) & 0xFFFFu);
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -120,9 +134,9 @@ __device__ __forceinline__ void load_stage_wave(const v4i* __restrict__ src, v4i
 // appends without coordinating with the others. cq[t] = keys in sub-buffer t.
 constexpr int kSub = kBuf / 4;
 
-// Merge the pending keys of one query into its list; returns the new bias
-// 2 thr - bits of that query (thr = distance of the K-th key, or bits + 1
-// while the list is not full).
+// Merge the pending keys of one query into its list; returns the query's new
+// threshold: the distance of the K-th key, or bits + 1 while the list is not
+// full (a candidate enters only at a distance below it).
 template <int NR>
 __device__ __forceinline__ int flush_sub(uint32_t* list_q, const uint32_t* buf_q,
                                          uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
@@ -136,7 +150,7 @@ __device__ __forceinline__ int flush_sub(uint32_t* list_q, const uint32_t* buf_q
   uint32_t R[NR];
   load_list<NR>(list_q, R, K, lane);  // in flight together with the pending keys
   const uint32_t kth = merge_desc_with<NR>(list_q, R, wave_sort_upper32_desc(x, lane), K, lane);
-  return kth == kKeyNone ? (int)bits + 2 : 2 * (int)(kth >> IB) - (int)bits;
+  return kth == kKeyNone ? (int)bits + 1 : (int)(kth >> IB);
 }
 
 // One tile job: rows [row0, row0 + nrows) against columns [cb, ce). The lists
@@ -305,22 +319,35 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
   }
   wave_sync();
 
+  // Query operands are +-1 bytes (s = 2q - 1), candidate operands {0, 1}
+  // bytes (a), so the product is <s, a> = popc(q & a) - popc(~q & a) and
+  // ham(q, a) = popc(q) - <s, a>. A candidate passes iff <s, a> + bias > 0
+  // with the query's current bias thr - popc(q), applied when the unit is
+  // filtered (so a threshold tightened since the contraction already counts).
+  // ({0, 1} candidate bytes toggle far fewer multiplier bits than +-1 bytes,
+  // which measurably raises the matrix cores' sustained rate.)
   v4i bq[QG][W];
-  v4i biasC[QG];
+  int biasQ[QG];
+  int popcq[QG];
   uint32_t qrow[QG], csub[QG];
 #pragma unroll
   for (int gq = 0; gq < QG; ++gq) {
     const uint32_t ql = q0 + 16 * gq + i16;
     const bool valid = ql < nrows;
     const uint32_t row = row0 + (valid ? ql : 0u);
+    int pc = 0;
 #pragma unroll
-    for (int s = 0; s < W; ++s) bq[gq][s] = code_chunk_pm1(codes, W, row, s, kq);
-    int bias = -(int)bits;  // absent row: acc = dot - bits <= 0, never passes
+    for (int s = 0; s < W; ++s) {
+      bq[gq][s] = code_chunk_pm1(codes, W, row, s, kq);
+      pc += __popcll(codes[(size_t)row * W + s]);
+    }
+    int bias = -(int)bits - 1;  // absent row: acc <= popc(q) - bits - 1 < 0, never passes
     if (valid) {
       const uint32_t kth = list_w[(16 * gq + i16) * K + K - 1];
-      bias = kth == kKeyNone ? (int)bits + 2 : 2 * (int)(kth >> IB) - (int)bits;
+      bias = (kth == kKeyNone ? (int)bits + 1 : (int)(kth >> IB)) - pc;
     }
-    biasC[gq] = v4i{bias, bias, bias, bias};
+    biasQ[gq] = bias;
+    popcq[gq] = pc;
     qrow[gq] = row0 + ql;
     csub[gq] = 0;
   }
@@ -340,60 +367,62 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
       const uint32_t i = __builtin_ctz(qm);
       qm &= qm - 1;
       const uint32_t qi = 16 * gq + i;
-      const int bias = flush_sub<NR>(
+      const int thr = flush_sub<NR>(
           list_w + qi * K, buf_w + qi * kBuf, __builtin_amdgcn_readlane(csub[gq], i),
           __builtin_amdgcn_readlane(csub[gq], 16 + i), __builtin_amdgcn_readlane(csub[gq], 32 + i),
           __builtin_amdgcn_readlane(csub[gq], 48 + i), K, lane, IB, bits);
       if (i16 == i) {
-        biasC[gq] = v4i{bias, bias, bias, bias};
+        biasQ[gq] = thr - popcq[gq];
         csub[gq] = 0;
       }
       wave_sync();
     }
   };
 
-  // Filter of the 16-code group starting at column cs, contracted with the
-  // biases bb - bits: append every candidate that beat its query's threshold.
+  // Filter of the 16-code group starting at column cs: the largest
+  // <s, a> + bias of a unit, and the appends of every candidate that beats its
+  // query's threshold.
+  auto max4b = [&](const v4i& acc, int gq) {
+    return max(max(acc[0], acc[1]), max(acc[2], acc[3])) + biasQ[gq];
+  };
   auto maxacc = [&](const v4i (&acc)[U][QG]) {
-    int mx = acc[0][0][0];
+    int mx = max4b(acc[0][0], 0);
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int gq = 0; gq < QG; ++gq)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) mx = max(mx, acc[u][gq][r]);
+      for (int gq = 0; gq < QG; ++gq) mx = max(mx, max4b(acc[u][gq], gq));
     return mx;
   };
-  auto append = [&](const v4i (&acc)[QG], const int (&bb)[QG], const uint32_t cs) {
+  auto append = [&](const v4i (&acc)[QG], const uint32_t cs) {
     const uint32_t c0 = cs + 4 * kq;
     const bool edge = cs < cb || cs + 16 > ce;   // group crosses the column range
     const bool diag = !rect && cs < qhi && cs + 16 > qlo;  // group holds some of the wave's rows
 #pragma unroll
     for (int gq = 0; gq < QG; ++gq) {
-      const int m4 = max(max(acc[gq][0], acc[gq][1]), max(acc[gq][2], acc[gq][3]));
-      if (!__any(m4 > 0)) continue;
-      // Pass flags as sign bits: p_r = 1 iff acc_r > lim_r. lim_r = 0, except
-      // (in the few groups on the column-range edge or holding the wave's own
-      // rows) a column outside [cb, ce) or the query's own row never passes.
+      if (!__any(max4b(acc[gq], gq) > 0)) continue;
+      // Pass flags as sign bits: p_r = 1 iff <s, a>_r + bias > lim_r. lim_r =
+      // 0, except (in the few groups on the column-range edge or holding the
+      // wave's own rows) a column outside [cb, ce) or the query's own row
+      // never passes (|<s, a> + bias| < 2^30, so the difference never wraps).
       int lim[4] = {0, 0, 0, 0};
       if (edge || diag) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const uint32_t col = c0 + r;
-          lim[r] = (col < cb || col >= ce || (!rect && col == qrow[gq])) ? 0x7FFFFFFF : 0;
+          lim[r] = (col < cb || col >= ce || (!rect && col == qrow[gq])) ? 0x3FFFFFFF : 0;
         }
       }
       uint32_t pass[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) pass[r] = (uint32_t)(lim[r] - acc[gq][r]) >> 31;
+      for (int r = 0; r < 4; ++r) pass[r] = (uint32_t)(lim[r] - (acc[gq][r] + biasQ[gq])) >> 31;
       const uint32_t c = pass[0] + pass[1] + pass[2] + pass[3];
       const uint64_t over = __ballot(csub[gq] + c > (uint32_t)kSub);
       if (over) flush_group(gq, over);
       uint32_t pos = (16 * gq + i16) * kBuf + kq * kSub + csub[gq];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        // (bb - acc) = 2 ham, so this is ham << IB | column
-        const uint32_t key = ((uint32_t)(bb[gq] - acc[gq][r]) << (IB - 1)) | (c0 + r - colbase);
+        // popc(q) - <s, a> = ham, so this is ham << IB | column
+        const uint32_t key = ((uint32_t)(popcq[gq] - acc[gq][r]) << IB) | (c0 + r - colbase);
         buf_w[pass[r] ? pos : discard] = key;
         pos += pass[r];
       }
@@ -407,27 +436,25 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
   // (never back to back), and `work(s)` places a share of the vector work
   // inside layer s. With U = 2 (two groups of 2 query tiles) four chains are
   // in flight, as many as with 4 query tiles.
-  auto issue_with = [&](v4i (&acc)[U][QG], int (&bb)[QG], const v4i (&a)[U][W], auto&& work) {
+  auto issue_with = [&](v4i (&acc)[U][QG], const v4i (&a)[U][W], auto&& work) {
 #pragma unroll
     for (int s = 0; s < W; ++s) {
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
         for (int gq = 0; gq < QG; ++gq)
-          acc[u][gq] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[u][s], bq[gq][s],
-                                                             s == 0 ? biasC[gq] : acc[u][gq], 0, 0, 0);
+          acc[u][gq] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+              a[u][s], bq[gq][s], s == 0 ? v4i{0, 0, 0, 0} : acc[u][gq], 0, 0, 0);
       work(s);
       // without a producer, a fence per layer keeps each operand read after
       // the products that free its registers; with one, the compiler's own
       // schedule of the reads was measured faster
       if constexpr (!PROD) __builtin_amdgcn_sched_barrier(0);
     }
-#pragma unroll
-    for (int gq = 0; gq < QG; ++gq) bb[gq] = biasC[gq][0] + (int)bits;
   };
-  auto append_unit = [&](const v4i (&acc)[U][QG], const int (&bb)[QG], const uint32_t cs) {
+  auto append_unit = [&](const v4i (&acc)[U][QG], const uint32_t cs) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) append(acc[u], bb, cs + 16 * u);
+    for (int u = 0; u < U; ++u) append(acc[u], cs + 16 * u);
   };
 
   // Units are contracted in a ping-pong of accumulators: unit j is issued
@@ -440,7 +467,6 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
   // registers layer s of unit j has just consumed, a whole unit ahead of its
   // use.
   v4i acc[2][U][QG];
-  int bb[2][QG];
   if constexpr (PROD) {
     // With a producer the unit stream runs across stage boundaries: the last
     // unit of stage st filters nothing new and reads the first unit of stage
@@ -451,9 +477,8 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int gq = 0; gq < QG; ++gq) acc[1][u][gq] = v4i{0, 0, 0, 0};  // nothing passes
-#pragma unroll
-    for (int gq = 0; gq < QG; ++gq) bb[1][gq] = 0;
+      for (int gq = 0; gq < QG; ++gq)
+        acc[1][u][gq] = v4i{-(1 << 29), -(1 << 29), -(1 << 29), -(1 << 29)};  // nothing passes
     uint32_t avail = 0;  // stages known to have landed
     bool have = false;   // `a` already holds the operands of the stage's first unit
     v4i a[U][W];         // operands of the unit being contracted (then of the next)
@@ -498,29 +523,26 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
         }
         __builtin_amdgcn_sched_barrier(0);
         v4i (&accP)[U][QG] = acc[(j + 1) & 1];  // the previous unit (stage st - 1's last for j = 0)
-        int mx = accP[0][0][0];
-        issue_with(acc[j & 1], bb[j & 1], a, [&](int s) {
+        int mx = -(1 << 29);
+        issue_with(acc[j & 1], a, [&](int s) {
 #pragma unroll
           for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int gq = 0; gq < QG; ++gq)
-              if ((u * QG + gq) % W == s)
-                mx = max(mx, max(max(accP[u][gq][0], accP[u][gq][1]),
-                                 max(accP[u][gq][2], accP[u][gq][3])));
+              if ((u * QG + gq) % W == s) mx = max(mx, max4b(accP[u][gq], gq));
           // (in the last unit these reads are made whether or not the next
           // stage has landed: reading a slot never disturbs the producer,
           // and operands read too early are read again at the stage start)
 #pragma unroll
           for (int u = 0; u < U; ++u) a[u][s] = nb[(u * W + s) * 64 + lane];
         });
-        if (__any(mx > 0))
-          append_unit(accP, bb[(j + 1) & 1], cs0 + 16 * U * j - 16 * U);
+        if (__any(mx > 0)) append_unit(accP, cs0 + 16 * U * j - 16 * U);
       }
       have = pf;
       slot = nslot;
     }
     if (nst > 0) {
-      if (__any(maxacc(acc[1]) > 0)) append_unit(acc[1], bb[1], cstart + nst * CT - 16 * U);
+      if (__any(maxacc(acc[1]) > 0)) append_unit(acc[1], cstart + nst * CT - 16 * U);
     }
   } else {
   uint32_t pend = 0xFFFFFFFFu;  // stage this wave copies and has not published
@@ -567,7 +589,7 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
 #pragma unroll
       for (int s = 0; s < W; ++s) a[u][s] = sb[(u * W + s) * 64 + lane];
     if (NU % 2 == 0 && st > 0) {  // last unit of stage st - 1
-      if (__any(maxacc(acc[1]) > 0)) append_unit(acc[1], bb[1], cs0 - 16 * U);
+      if (__any(maxacc(acc[1]) > 0)) append_unit(acc[1], cs0 - 16 * U);
     }
 #pragma unroll
     for (int j = 0; j < NU; ++j) {
@@ -590,29 +612,27 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
       };
       if (j > 0) {
         v4i (&accP)[U][QG] = acc[(j - 1) & 1];
-        int mx = accP[0][0][0];
-        issue_with(acc[j & 1], bb[j & 1], a, [&](int s) {
+        int mx = -(1 << 29);
+        issue_with(acc[j & 1], a, [&](int s) {
 #pragma unroll
           for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int gq = 0; gq < QG; ++gq)
-              if ((u * QG + gq) % W == s)
-                mx = max(mx, max(max(accP[u][gq][0], accP[u][gq][1]),
-                                 max(accP[u][gq][2], accP[u][gq][3])));
+              if ((u * QG + gq) % W == s) mx = max(mx, max4b(accP[u][gq], gq));
           prefetch(s);
         });
-        if (__any(mx > 0)) append_unit(accP, bb[(j - 1) & 1], cs0 + 16 * U * (j - 1));
+        if (__any(mx > 0)) append_unit(accP, cs0 + 16 * U * (j - 1));
       } else {
-        issue_with(acc[0], bb[0], a, prefetch);
+        issue_with(acc[0], a, prefetch);
       }
     }
     if (NU % 2 != 0) {
       if (__any(maxacc(acc[(NU - 1) & 1]) > 0))
-        append_unit(acc[(NU - 1) & 1], bb[(NU - 1) & 1], cs0 + 16 * U * (NU - 1));
+        append_unit(acc[(NU - 1) & 1], cs0 + 16 * U * (NU - 1));
     }
   }
   if (NU % 2 == 0 && nst > 0) {
-    if (__any(maxacc(acc[1]) > 0)) append_unit(acc[1], bb[1], cstart + nst * CT - 16 * U);
+    if (__any(maxacc(acc[1]) > 0)) append_unit(acc[1], cstart + nst * CT - 16 * U);
   }
   }
   BDG_WAIT_VMCNT(0);  // no stage copy of this wave is still in flight
