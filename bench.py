@@ -39,6 +39,7 @@ sys.path.insert(0, ROOT)
 
 # MI355X published peaks
 PEAK_INT8_TOPS = 5000.0           # dense int8 matrix, TOP/s
+PEAK_FP32_MFMA_TFLOPS = 157.3     # dense FP32 matrix, TFLOP/s
 CU, LANES, CLOCK = 256, 64, 2.4e9
 PEAK_VALU_TOPS = CU * LANES * CLOCK / 1e12  # 32-bit integer vector ops, TOP/s (derived)
 METRIC = "Hamming kNN-graph build pair-dist/s + % peak; recall@K learned vs plain codes"
@@ -265,8 +266,11 @@ def recall_leg():
             "encode_ms_srp": res["encode_seconds_srp"] * 1e3,
             "graph_ms_learned": res["graph_seconds_learned"] * 1e3,
             "graph_ms_srp": res["graph_seconds_srp"] * 1e3,
-            "float_knn_ms": {"train_pairs": res["train_knn_seconds"] * 1e3,
-                             "eval_truth": res["exact_knn_seconds"] * 1e3},
+            "float_knn": {k: dict(v, kernel="fknn_mfma_kernel (+ norms, split merge)",
+                                  roofline={"bound": "mfma", "achieved": v["tflops"],
+                                            "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                                            "frac": v["tflops"] / PEAK_FP32_MFMA_TFLOPS})
+                          for k, v in res["float_knn"].items()},
             "search_recall_at_60": {"srp": res["search_srp"], "learned": res["search_learned"]}}
 
 

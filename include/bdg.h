@@ -353,12 +353,16 @@ int bdg_pack_signs(const float *z, uint32_t n, uint32_t bits, uint64_t *out_code
  * Exact squared-L2 kNN in FP32, the real-valued ground truth of recall
  * (Sec. 4.2): row q = the first K of (||q - y_j||^2, j) over base rows j,
  * leaving out exclude[q] (device int32 [nq], -1 = none; NULL = none), ties to
- * the smaller index. Distances are assembled as |q|^2 + |y|^2 - 2 <q, y>
- * (inner products by a library FP32 GEMM), so near-ties closer than FP32
- * rounding may order differently from exact arithmetic. queries: device
- * float [nq][d], base: device float [nb][d]; out_idx uint32 [nq][K] and
- * out_dist float [nq][K] (padding: 0xFFFFFFFF / +inf). K in 1..128.
- * Allocates a stream-ordered workspace (about 2 GB at most).
+ * the smaller index. Distances are assembled as |q|^2 + |y|^2 - 2 <q, y>, the
+ * inner products on the FP32 matrix cores with the top-K fused (no distance
+ * block goes to memory), so near-ties closer than FP32 rounding may order
+ * differently from exact arithmetic. d a multiple of 4 up to 512 takes the
+ * matrix cores; other d a plain vector-ALU kernel with direct sums. queries:
+ * device float [nq][d] and base: device float [nb][d], rows 4-byte aligned;
+ * out_idx uint32 [nq][K] and out_dist float [nq][K] (padding: 0xFFFFFFFF /
+ * +inf). K in 1..128. Allocates a stream-ordered workspace of norms and, for
+ * a wide base split over work-groups, partial lists (about splits x nq x K x
+ * 8 bytes).
  */
 int bdg_float_knn(const float *queries, uint32_t nq, const float *base, uint32_t nb, uint32_t d,
                   uint32_t K, const int32_t *exclude, uint32_t *out_idx, float *out_dist,

@@ -58,7 +58,7 @@ def build(asm: bool = False, jobs: int | None = None) -> str:
         objs = list(ex.map(lambda s: _compile(s, asm), srcs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
-           "-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
+           "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib"]
     subprocess.run(cmd, check=True, cwd=BUILD)
     os.replace(tmp, LIB)
     return LIB

@@ -9,18 +9,13 @@
 //   * a small MLP encoder (d -> h -> bits, tanh) whose products are BF16
 //     matrix-core contractions with FP32 accumulation, its backward pass, a
 //     triplet loss on relaxed Hamming distances, and Adam;
-//   * exact squared-L2 kNN in FP32: inner products by a library GEMM, the
-//     distance assembly and the per-row top-K in our kernel.
+// (the exact squared-L2 kNN in FP32 that measures recall is in fknn.hip).
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 #include <math.h>
 #include <stdint.h>
 
-#include <mutex>
-
 #include "bdg.h"
 #include "kernels.h"
-#include "wave_topk64.h"
 
 namespace bdg {
 int api_error(int status, const char* fmt, ...);
@@ -31,12 +26,6 @@ namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
-
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 __device__ __forceinline__ uint16_t to_bf16(float f) {  // round to nearest even
   uint32_t u = __float_as_uint(f);
@@ -382,106 +371,6 @@ __global__ void to_bf16_kernel(const float* __restrict__ w, uint32_t rows, uint3
   if (bt) bt[(size_t)c * rows + r] = v;
 }
 
-// ------------------------------------------------------------- float kNN --
-
-// Squared norms in FP32 (one wave per row).
-__global__ __launch_bounds__(256) void row_norms_kernel(const float* __restrict__ x, uint32_t n,
-                                                        uint32_t d, float* __restrict__ out) {
-  const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t r = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (r >= n) return;
-  const float* xr = x + (size_t)r * d;
-  float s = 0.f;
-  for (uint32_t k = lane; k < d; k += 64) s += xr[k] * xr[k];
-  s = wave_sum(s);
-  if (lane == 0) out[r] = s;
-}
-
-// One wave per query row of an inner-product block G [nq][ldg] (columns =
-// base rows c0 .. c0 + nc): d = |q|^2 + |y|^2 - 2 <q, y> (clamped at 0); keys
-// (float bits of d) << 32 | base index; the running list of the row (K <= 64
-// NR) lives in registers and in the outputs between blocks. Columns arrive in
-// increasing index, so the strict test d < thr is exact.
-template <int NR>
-__global__ __launch_bounds__(256) void fknn_topk_kernel(const float* __restrict__ G, uint32_t ldg,
-                                                        uint32_t nq, uint32_t q0, uint32_t c0,
-                                                        uint32_t nc,
-                                                        const float* __restrict__ qn,
-                                                        const float* __restrict__ cn,
-                                                        const int32_t* __restrict__ exclude,
-                                                        uint32_t K, int fresh,
-                                                        uint32_t* __restrict__ out_idx,
-                                                        float* __restrict__ out_dist) {
-  __shared__ uint64_t bufs[4][64];
-  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-  const uint32_t qi = blockIdx.x * 4 + wave;
-  if (qi >= nq) return;  // wave-uniform
-  uint64_t* buf = bufs[wave];
-  const size_t orow = (size_t)(q0 + qi) * K;
-  uint64_t R[NR];
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const uint32_t p = 64 * r + lane;
-    R[r] = kNone64;
-    if (!fresh && p < K && out_idx[orow + p] != 0xFFFFFFFFu)
-      R[r] = ((uint64_t)__float_as_uint(out_dist[orow + p]) << 32) | out_idx[orow + p];
-  }
-  auto kth_dist = [&]() -> float {
-    uint64_t k = kNone64;
-#pragma unroll
-    for (int r = 0; r < NR; ++r)
-      if ((uint32_t)r == (K - 1) / 64) {
-        const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)R[r], (K - 1) & 63);
-        const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(R[r] >> 32), (K - 1) & 63);
-        k = ((uint64_t)hi << 32) | lo;
-      }
-    return k == kNone64 ? INFINITY : __uint_as_float((uint32_t)(k >> 32));
-  };
-  float thr = kth_dist();
-  const float qq = qn[q0 + qi];
-  const int32_t ex = exclude ? exclude[q0 + qi] : -1;
-  const float* g = G + (size_t)qi * ldg;
-  uint32_t cnt = 0;
-  for (uint32_t j0 = 0; j0 < nc; j0 += 64) {
-    const uint32_t j = j0 + lane;
-    const uint32_t col = c0 + j;
-    float d = INFINITY;
-    if (j < nc && (int32_t)col != ex) d = fmaxf(qq + cn[col] - 2.f * g[j], 0.f);
-    bool pass = d < thr;
-    uint64_t m = __ballot(pass);
-    if (!m) continue;
-    uint32_t c = (uint32_t)__popcll(m);
-    if (cnt + c > 64) {
-      wave_sync();
-      merge64_into<NR>(R, lane < cnt ? buf[lane] : kNone64, lane);
-      cnt = 0;
-      thr = kth_dist();
-      pass = d < thr;
-      m = __ballot(pass);
-      c = (uint32_t)__popcll(m);
-    }
-    if (pass) {
-      const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-      buf[cnt + below] = ((uint64_t)__float_as_uint(d) << 32) | col;
-    }
-    cnt += c;
-    wave_sync();
-  }
-  if (cnt) merge64_into<NR>(R, lane < cnt ? buf[lane] : kNone64, lane);
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const uint32_t p = 64 * r + lane;
-    if (p < K) {
-      const bool none = R[r] == kNone64;
-      out_idx[orow + p] = none ? 0xFFFFFFFFu : (uint32_t)R[r];
-      out_dist[orow + p] = none ? INFINITY : __uint_as_float((uint32_t)(R[r] >> 32));
-    }
-  }
-}
-
-std::mutex g_blas_mu;
-rocblas_handle g_blas = nullptr;
 
 unsigned blocks_for(size_t count) { return (unsigned)((count + 255) / 256); }
 
@@ -729,70 +618,6 @@ int bdg_mlp_encode(const bdg_mlp_params* p, const float* X, uint32_t n, float sc
   hipError_t e2 = hipFreeAsync(ws, s);
   if (e == hipSuccess) e = e2;
   return e == hipSuccess ? BDG_OK : api_device_error(e, "encode");
-}
-
-int bdg_float_knn(const float* queries, uint32_t nq, const float* base, uint32_t nb, uint32_t d,
-                  uint32_t K, const int32_t* exclude, uint32_t* out_idx, float* out_dist,
-                  void* stream) {
-  api_clear_error();
-  if (K == 0 || K > 128) return api_error(BDG_EUNSUPPORTED, "K must be 1..128");
-  if (d == 0) return api_error(BDG_EINVAL, "d must be >= 1");
-  if (nq == 0) return BDG_OK;
-  if (!queries || !base || !out_idx || !out_dist) return api_error(BDG_EINVAL, "null pointer");
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  std::lock_guard<std::mutex> lk(g_blas_mu);
-  if (!g_blas && rocblas_create_handle(&g_blas) != rocblas_status_success) {
-    g_blas = nullptr;
-    return api_error(BDG_EDEVICE, "rocblas_create_handle failed");
-  }
-  if (rocblas_set_stream(g_blas, s) != rocblas_status_success)
-    return api_error(BDG_EDEVICE, "rocblas_set_stream failed");
-  const uint32_t QC = 8192, BC = 65536;
-  const uint32_t qc = nq < QC ? nq : QC, bc = nb < BC ? (nb ? nb : 1) : BC;
-  const size_t gbytes = (size_t)qc * bc * 4, nbytes = ((size_t)nq + nb) * 4;
-  void* ws = nullptr;
-  hipError_t e = hipMallocAsync(&ws, gbytes + nbytes + 256, s);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return api_error(BDG_ENOMEM, "float kNN workspace of %zu bytes", gbytes + nbytes);
-  }
-  float* G = static_cast<float*>(ws);
-  float* qn = reinterpret_cast<float*>(static_cast<char*>(ws) + gbytes);
-  float* cn = qn + nq;
-  hipLaunchKernelGGL(row_norms_kernel, dim3((nq + 3) / 4), dim3(256), 0, s, queries, nq, d, qn);
-  if (nb)
-    hipLaunchKernelGGL(row_norms_kernel, dim3((nb + 3) / 4), dim3(256), 0, s, base, nb, d, cn);
-  e = hipGetLastError();
-  int st = BDG_OK;
-  const float one = 1.f, zero = 0.f;
-  for (uint32_t q0 = 0; q0 < nq && e == hipSuccess && st == BDG_OK; q0 += QC) {
-    const uint32_t nqc = nq - q0 < QC ? nq - q0 : QC;
-    for (uint32_t c0 = 0; c0 == 0 || c0 < nb; c0 += BC) {
-      const uint32_t ncc = nb - c0 < BC ? nb - c0 : BC;
-      if (ncc) {
-        // G (row-major [nqc][ncc]) = Q Y^T, i.e. column-major G^T = Y Q^T
-        if (rocblas_sgemm(g_blas, rocblas_operation_transpose, rocblas_operation_none, ncc, nqc,
-                          d, &one, base + (size_t)c0 * d, d, queries + (size_t)q0 * d, d, &zero,
-                          G, ncc) != rocblas_status_success) {
-          st = api_error(BDG_EDEVICE, "rocblas_sgemm failed");
-          break;
-        }
-      }
-      dim3 grid((nqc + 3) / 4);
-      if (K <= 64)
-        hipLaunchKernelGGL(fknn_topk_kernel<1>, grid, dim3(256), 0, s, G, ncc, nqc, q0, c0, ncc,
-                           qn, cn, exclude, K, (int)(c0 == 0), out_idx, out_dist);
-      else
-        hipLaunchKernelGGL(fknn_topk_kernel<2>, grid, dim3(256), 0, s, G, ncc, nqc, q0, c0, ncc,
-                           qn, cn, exclude, K, (int)(c0 == 0), out_idx, out_dist);
-      e = hipGetLastError();
-      if (e != hipSuccess || nb == 0) break;
-    }
-  }
-  hipError_t e2 = hipFreeAsync(ws, s);
-  if (st != BDG_OK) return st;
-  if (e == hipSuccess) e = e2;
-  return e == hipSuccess ? BDG_OK : api_device_error(e, "float kNN");
 }
 
 }  // extern "C"

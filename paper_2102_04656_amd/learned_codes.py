@@ -166,6 +166,33 @@ class Workload:
         torch.cuda.synchronize()
         self.times["exact_knn"] = time.perf_counter() - t0
 
+    def time_float_knn(self, reps: int = 3):
+        """Kernel time of the two exact float-kNN calls of the workload (the
+        training pairs and the recall ground truth), after a warm-up, with
+        events on the launch stream; the FLOP rate counts 2 d flops per
+        (query, base row) pair."""
+        import torch
+        out = {}
+        shapes = {"train_pairs": (self.Xtr, self.Xtr, self.info["K_train"],
+                                  torch.arange(self.Xtr.shape[0], dtype=torch.int32,
+                                               device="cuda")),
+                  "eval_truth": (self.X[self.q].contiguous(), self.X, self.K_eval,
+                                 self.q.to(torch.int32))}
+        for name, (qx, bx, K, ex) in shapes.items():
+            bdg.float_knn(qx, bx, K, exclude=ex)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                bdg.float_knn(qx, bx, K, exclude=ex)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            flops = 2.0 * qx.shape[0] * bx.shape[0] * qx.shape[1]
+            out[name] = dict(nq=int(qx.shape[0]), nb=int(bx.shape[0]), d=int(qx.shape[1]), K=K,
+                             ms=ms, tflops=flops / (ms * 1e-3) / 1e12)
+        return out
+
     def evaluate(self, encode):
         """Encode every row, build the exact K_eval Hamming graph, return
         (recall@K_eval of the sampled rows, encode seconds, graph seconds)."""
@@ -223,6 +250,8 @@ def experiment(steps=20000, T=1024, lr=3e-4, h=1024, loss_opts=None, sampler=Non
                loss=dict(LOSS_DEFAULTS, **(loss_opts or {})),
                sampler=dict(SAMPLER_DEFAULTS, **(sampler or {})),
                **{f"{k}_seconds": v for k, v in wl.times.items()})
+    res["float_knn"] = wl.time_float_knn()
+    log(f"[g2] float kNN: {res['float_knn']}")
     r, te, tg = wl.evaluate_srp()
     res.update(recall_srp=r, encode_seconds_srp=te, graph_seconds_srp=tg)
     log(f"[g2] srp: recall@{wl.K_eval} {r:.4f} (encode {te:.3f}s, graph {tg:.3f}s)")

@@ -142,16 +142,31 @@ def test_adam_vs_fp64():
 
 
 def check_float_knn(q, base, K, gi, gd, rows, exclude=None):
-    """GPU rows are exact kNN up to FP32 near-ties."""
+    """GPU rows against the FP64 oracle (Sec. 4.2: exact float kNN). The GPU
+    assembles FP32 distances as |q|^2 + |y|^2 - 2 <q, y>, so a distance
+    carries an absolute rounding error of order eps_32 (|q|^2 + |y|^2), and
+    two candidates closer than that may swap. The band used here is the
+    larger of 1e-5 relative and 1e-6 (|q|^2 + max |y|^2) absolute. Every row
+    must hold the right distances in order (its indices' FP64 distances,
+    sorted, equal the oracle's within the band), its FP32 distances must be
+    the FP64 ones within the band, and wherever its index differs from the
+    oracle's at a position the two candidates there must be FP64 near-ties
+    within the band. Returns the number of rows identical to the oracle's."""
     same = 0
+    ymax = float((base.astype(np.float64) ** 2).sum(axis=1).max()) if len(base) else 0.0
     for r in rows:
         ex = None if exclude is None else np.array([exclude[r]])
         wi, wd = L.float_knn(q[r:r + 1], base, K, exclude=ex)
+        qq = float((q[r].astype(np.float64) ** 2).sum())
+        band = np.maximum(1e-5 * wd[0], 1e-6 * (qq + ymax))
         d_gpu = ((base[gi[r]].astype(np.float64) - q[r].astype(np.float64)) ** 2).sum(axis=1)
-        assert np.allclose(np.sort(d_gpu), wd[0], rtol=1e-5, atol=1e-6), f"row {r}"
-        assert np.allclose(gd[r], wd[0], rtol=1e-4, atol=1e-4)
+        assert (np.abs(np.sort(d_gpu) - wd[0]) <= band).all(), f"row {r}"
+        assert (np.abs(gd[r] - wd[0]) <= band).all(), f"row {r} distances"
         assert len(set(gi[r].tolist())) == K and (exclude is None or exclude[r] not in gi[r])
-        same += np.array_equal(gi[r], wi[0])
+        diff = np.nonzero(gi[r] != wi[0])[0]
+        for p in diff:  # a swap between FP64 near-ties, nothing else
+            assert abs(d_gpu[p] - wd[0][p]) <= band[p], (r, p)
+        same += diff.size == 0
     return same
 
 
@@ -161,12 +176,13 @@ def test_float_knn_small_full():
                                              exclude=cu(np.arange(2000, dtype=np.int32))))
     gi = gi.view(np.uint32)
     same = check_float_knn(x, x, 10, gi, gd, range(2000), exclude=np.arange(2000))
-    assert same >= 1990
+    print(f"[float-knn] {same} of 2000 rows identical to the oracle, the rest near-tie swaps")
 
 
 def test_float_knn_blocks_and_padding():
-    # more queries than one query chunk (8192) and more base rows than one
-    # column block (65536): the running lists cross blocks
+    # 9,000 queries (141 work-groups of 64, the last one ragged) against 70,000
+    # base rows split over work-groups (partial lists merged), K = 33 (two
+    # list registers per lane)
     x = datagen.gmm_features(70_000, 32, n_comp=300, centre_std=2.0, seed=10)
     q = x[:9000]
     gi, gd = (host(t) for t in bdg.float_knn(cu(q), cu(x), 33,
@@ -201,3 +217,25 @@ def test_learned_codes_beat_srp_on_mixture():
     diff = datagen.unpack_bits(codes) != (z2 > 0)
     # bf16 operands: a bit may differ only where FP64 Z2 is near zero
     assert (np.abs(z2[diff]) < 0.05).all() and diff.mean() < 0.01
+
+
+@pytest.mark.parametrize("nq,nb,d,K,seed", [
+    (70, 5000, 512, 64, 21),   # one work-group, 512 dimensions (32 chunks), one split
+    (300, 40000, 128, 100, 22),  # several splits, K = 100
+    (130, 3000, 36, 5, 23),    # d not a multiple of 16 (zero-padded chunks)
+    (50, 2000, 30, 8, 24),     # d not a multiple of 4: the vector-ALU kernel
+    (40, 1500, 600, 16, 25),   # d > 512: the vector-ALU kernel
+    (17, 9, 64, 12, 26),       # fewer base rows than K: padding
+])
+def test_float_knn_shapes(nq, nb, d, K, seed):
+    g = np.random.default_rng(seed)
+    centres = g.standard_normal((20, d)) * 2.0
+    x = (centres[g.integers(0, 20, nb)] + g.standard_normal((nb, d))).astype(np.float32)
+    q = (x[g.integers(0, nb, nq)] + 0.1 * g.standard_normal((nq, d))).astype(np.float32)
+    print(f"[float-knn] nq={nq} nb={nb} d={d} K={K}", flush=True)
+    gi, gd = (host(t) for t in bdg.float_knn(cu(q), cu(x), K))
+    gi = gi.view(np.uint32)
+    Kr = min(K, nb)
+    if Kr < K:
+        assert (gi[:, Kr:] == 0xFFFFFFFF).all() and np.isinf(gd[:, Kr:]).all()
+    check_float_knn(q, x, Kr, gi[:, :Kr], gd[:, :Kr], range(nq))
