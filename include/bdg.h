@@ -92,8 +92,19 @@ typedef struct bdg_knn_opts {
                                 and sets the stall flag (0 = default, seconds;
                                 a correct run never reaches it). Lowering it
                                 is a test hook for the give-up path */
-    uint32_t reserved[3];
+    uint32_t tile_schedule;  /* matrix-core tile schedule (BDG_SCHEDULE_*; the
+                                graph is the same under every schedule);
+                                default 0, or the autotuned one with path AUTO
+                                and col_block 0 */
+    uint32_t reserved[2];
 } bdg_knn_opts;
+
+/* Tile schedules of the matrix-core build and of batched plans. They differ
+ * in the LDS split between the rows' pending-key buffers and the stage ring
+ * of candidate operands, never in the result. */
+#define BDG_SCHEDULE_DEFAULT 0   /* 32 pending keys per row */
+#define BDG_SCHEDULE_DEEP_RING 1 /* 16 pending keys per row, more stages in
+                                    flight; codes of 128, 256 or 512 bits */
 
 /* ---------------------------------------------------------------- build --- */
 
@@ -293,6 +304,7 @@ typedef struct bdg_batch_plan bdg_batch_plan;
 typedef struct bdg_batch_info {
     uint32_t shards, rows, work_items, workgroups;
     int32_t order;         /* BDG_ORDER_* */
+    int32_t schedule;      /* BDG_SCHEDULE_* */
     uint64_t pairs;        /* sum over shards of n_s (n_s - 1) */
     size_t device_bytes;   /* device memory held by the plan */
 } bdg_batch_info;
@@ -308,6 +320,9 @@ int bdg_batch_plan_create(const uint64_t *offsets, uint32_t S, uint32_t bits, ui
                           const bdg_knn_opts *opts, bdg_batch_plan **plan);
 void bdg_batch_plan_destroy(bdg_batch_plan *plan);
 int bdg_batch_plan_info(const bdg_batch_plan *plan, bdg_batch_info *info);
+/* Change the tile schedule (BDG_SCHEDULE_*; drops a captured graph);
+ * BDG_EUNSUPPORTED if the schedule is not built for the plan's code length. */
+int bdg_batch_plan_set_schedule(bdg_batch_plan *plan, int schedule);
 /* Change the work order (re-uploads the work list; drops a captured graph).
  * Waits for all work queued on the device first, so a launch of the plan
  * still in flight on any stream finishes with the old list. A plan holds one

@@ -51,7 +51,8 @@ class KnnOpts(ctypes.Structure):
         ("n_tile_events", ctypes.c_uint32),
         ("tile_events", ctypes.c_void_p),
         ("wait_limit", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 3),
+        ("tile_schedule", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 2),
     ]
 
 
@@ -62,12 +63,14 @@ class BatchInfo(ctypes.Structure):
         ("work_items", ctypes.c_uint32),
         ("workgroups", ctypes.c_uint32),
         ("order", ctypes.c_int32),
+        ("schedule", ctypes.c_int32),
         ("pairs", ctypes.c_uint64),
         ("device_bytes", ctypes.c_size_t),
     ]
 
 
 ORDER_LONGEST_FIRST, ORDER_SHARD = 0, 1
+SCHEDULE_DEFAULT, SCHEDULE_DEEP_RING = 0, 1
 
 
 class MlpParams(ctypes.Structure):
@@ -125,6 +128,7 @@ _SIGS = {
     "bdg_batch_plan_destroy": [_p],
     "bdg_batch_plan_info": [_p, _p],
     "bdg_batch_plan_set_order": [_p, ctypes.c_int],
+    "bdg_batch_plan_set_schedule": [_p, ctypes.c_int],
     "bdg_build_knn_batched_plan": [_p, _p, _p, _p, _p],
     "bdg_build_knn_batched_graph": [_p, _p, _p, _p, _p],
     "bdg_build_knn_batched_ex": [_p, _p, _u32, _u32, _u32, _p, _p, _p, _p],
@@ -250,7 +254,8 @@ def bdg_version() -> int:
 # ------------------------------------------------------------- conveniences
 
 def build_knn(codes, K: int, bits: int | None = None, path: int = PATH_AUTO,
-              row_block: int = 0, col_block: int = 0, stream=None, out=None):
+              row_block: int = 0, col_block: int = 0, stream=None, out=None,
+              schedule: int = SCHEDULE_DEFAULT):
     """Exact Hamming kNN graph of ``codes`` (int64 ``[n][W]`` on the GPU).
 
     Returns ``(idx int32 [n][K], dist int16 [n][K])`` on the GPU (uint32 /
@@ -261,7 +266,7 @@ def build_knn(codes, K: int, bits: int | None = None, path: int = PATH_AUTO,
     if out is None:
         out = (torch.empty((n, K), dtype=torch.int32, device=codes.device),
                torch.empty((n, K), dtype=torch.int16, device=codes.device))
-    opts = make_opts(path=path, row_block=row_block, col_block=col_block)
+    opts = make_opts(path=path, row_block=row_block, col_block=col_block, tile_schedule=schedule)
     _check(bdg_build_knn_ex(codes, n, bits, K, out[0], out[1], opts, stream))
     return out
 
@@ -355,12 +360,13 @@ class BatchPlan:
     """A plan for building the graphs of many shards in one persistent launch
     (``bdg_batch_plan_*``). ``offsets`` is a host array of S + 1 row offsets."""
 
-    def __init__(self, offsets, bits: int, K: int, order: int = ORDER_LONGEST_FIRST):
+    def __init__(self, offsets, bits: int, K: int, order: int = ORDER_LONGEST_FIRST,
+                 schedule: int = SCHEDULE_DEFAULT):
         off, ptr = _host_offsets(offsets)
         self.offsets, self.bits, self.K = off, bits, K
         self.S = off.size - 1
         h = ctypes.c_void_p()
-        o = make_opts(tile_variant=order)
+        o = make_opts(tile_variant=order, tile_schedule=schedule)
         _check(lib().bdg_batch_plan_create(ptr, self.S, bits, K, ctypes.byref(o), ctypes.byref(h)))
         self.handle = h
 
@@ -371,6 +377,9 @@ class BatchPlan:
 
     def set_order(self, order: int):
         _check(lib().bdg_batch_plan_set_order(self.handle, order))
+
+    def set_schedule(self, schedule: int):
+        _check(lib().bdg_batch_plan_set_schedule(self.handle, schedule))
 
     def outputs(self, device="cuda"):
         import torch
@@ -420,7 +429,7 @@ def autotune_build(codes, K: int, bits: int | None = None, row_block: int = 0, s
     out = (torch.empty((n, K), dtype=torch.int32, device=codes.device),
            torch.empty((n, K), dtype=torch.int16, device=codes.device))
     o = make_opts(row_block=row_block)
-    rep = ctypes.create_string_buffer(4096)
+    rep = ctypes.create_string_buffer(8192)
     _check(lib().bdg_autotune_build(_ptr(codes), n, bits, K, _ptr(out[0]), _ptr(out[1]),
                                     ctypes.byref(o), _stream(stream), rep, len(rep)))
     return o, rep.value.decode()

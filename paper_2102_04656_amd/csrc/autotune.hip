@@ -3,11 +3,12 @@
 // The paper tunes only the number of centres and the candidate budget of the
 // divide-and-conquer (Sec. 4.5); the schedule knobs here are the GPU's own:
 // which distance tile runs (vector-ALU popcount or int8 matrix cores), the
-// column-block width of the blockwise build (the window of candidates all
-// work-groups stream through L2 together), and the work order of a batched
-// launch. Every candidate computes the same graph (exact, (distance, index)
-// order), so tuning never changes results; candidates are timed with HIP
-// events on the caller's stream and the fastest is kept.
+// column-block width of the persistent build (the window of candidates all
+// work-groups stream through L2 together), the tile schedule (the LDS split
+// between the rows' pending-key buffers and the stage ring), and the work
+// order of a batched launch. Every candidate computes the same graph (exact,
+// (distance, index) order), so tuning never changes results; candidates are
+// timed with HIP events on the caller's stream and the fastest is kept.
 //
 // Tuned single builds are remembered per (code length, K, size bucket) for
 // the process, and appended as one JSON object per line to the file named by
@@ -38,6 +39,7 @@ namespace {
 struct Tuned {
   int path;
   uint32_t col_block;
+  int schedule;
 };
 
 std::mutex g_mu;
@@ -60,11 +62,11 @@ void load_cache_locked() {
   char line[512];
   while (fgets(line, sizeof line, f)) {
     unsigned bits = 0, K = 0, bucket = 0, cb = 0;
-    int p = 0;
+    int p = 0, sc = 0;
     if (strstr(line, "\"kind\": \"build\"") &&
         sscanf(strstr(line, "\"bits\""), "\"bits\": %u, \"K\": %u, \"bucket\": %u, \"path\": %d, "
-               "\"col_block\": %u", &bits, &K, &bucket, &p, &cb) == 5)
-      g_cache[std::make_tuple(bits, K, bucket)] = Tuned{p, cb};
+               "\"col_block\": %u, \"schedule\": %d", &bits, &K, &bucket, &p, &cb, &sc) == 6)
+      g_cache[std::make_tuple(bits, K, bucket)] = Tuned{p, cb, sc};
   }
   fclose(f);
 }
@@ -111,13 +113,15 @@ int time_ms(F&& fn, hipStream_t stream, int reps, float* ms) {
 }  // namespace
 
 // The tuned schedule of a single build, if any (path AUTO, col_block 0).
-bool tuned_schedule(uint32_t n, uint32_t bits, uint32_t K, int* path, uint32_t* col_block) {
+bool tuned_schedule(uint32_t n, uint32_t bits, uint32_t K, int* path, uint32_t* col_block,
+                    int* schedule) {
   std::lock_guard<std::mutex> lk(g_mu);
   load_cache_locked();
   auto it = g_cache.find(std::make_tuple(bits, K, size_bucket(n)));
   if (it == g_cache.end()) return false;
   *path = it->second.path;
   *col_block = it->second.col_block;
+  *schedule = it->second.schedule;
   return true;
 }
 
@@ -136,24 +140,32 @@ int bdg_autotune_build(const uint64_t* codes, uint32_t n, uint32_t bits, uint32_
   struct Cand {
     int path;
     uint32_t col_block;
+    int schedule;
     float ms;
   };
-  std::vector<Cand> cands = {{BDG_PATH_MFMA, 65536, 0}, {BDG_PATH_MFMA, 131072, 0},
-                             {BDG_PATH_MFMA, 262144, 0}, {BDG_PATH_POPC, 131072, 0}};
-  // workspace large enough for every candidate
+  std::vector<Cand> cands;
+  for (int sc = 0; sc < bdg::kTileSchedules; ++sc)
+    for (uint32_t cb : {131072u, 262144u, 524288u}) cands.push_back({BDG_PATH_MFMA, cb, sc, 0.f});
+  cands.push_back({BDG_PATH_POPC, 131072u, 0, 0.f});
+  // the candidates this build supports, and one workspace large enough for all
   size_t ws = 0;
   std::vector<Cand> ok;
   for (const Cand& c : cands) {
     bdg_knn_opts o = *opts;
     o.path = c.path;
     o.col_block = c.col_block;
+    o.tile_schedule = (uint32_t)c.schedule;
     o.workspace = nullptr;
     o.workspace_bytes = 0;
     o.n_tile_events = 0;
     o.tile_events = nullptr;
     size_t b = 0;
     if (bdg_build_knn_workspace_size(n, bits, K, &o, &b) == BDG_OK) {
-      ok.push_back(c);
+      // a column block wider than the input is the same schedule as the input's width
+      bool dup = false;
+      for (const Cand& d : ok)
+        dup |= d.path == c.path && d.schedule == c.schedule && d.col_block >= n && c.col_block >= n;
+      if (!dup) ok.push_back(c);
       if (b > ws) ws = b;
     }
   }
@@ -173,6 +185,7 @@ int bdg_autotune_build(const uint64_t* codes, uint32_t n, uint32_t bits, uint32_
     bdg_knn_opts o = *opts;
     o.path = ok[i].path;
     o.col_block = ok[i].col_block;
+    o.tile_schedule = (uint32_t)ok[i].schedule;
     o.workspace = buf;
     o.workspace_bytes = ws;
     o.n_tile_events = 0;
@@ -186,25 +199,27 @@ int bdg_autotune_build(const uint64_t* codes, uint32_t n, uint32_t bits, uint32_
   if (st != BDG_OK) return st;
   opts->path = ok[best].path;
   opts->col_block = ok[best].col_block;
+  opts->tile_schedule = (uint32_t)ok[best].schedule;
   {
     std::lock_guard<std::mutex> lk(bdg::g_mu);
     bdg::load_cache_locked();
     bdg::g_cache[std::make_tuple(bits, K, bdg::size_bucket(n))] =
-        bdg::Tuned{ok[best].path, ok[best].col_block};
+        bdg::Tuned{ok[best].path, ok[best].col_block, ok[best].schedule};
   }
   char line[512];
   snprintf(line, sizeof line,
            "{\"kind\": \"build\", \"bits\": %u, \"K\": %u, \"bucket\": %u, \"path\": %d, "
-           "\"col_block\": %u, \"n\": %u, \"ms\": %.3f}",
-           bits, K, bdg::size_bucket(n), ok[best].path, ok[best].col_block, n, ok[best].ms);
+           "\"col_block\": %u, \"schedule\": %d, \"n\": %u, \"ms\": %.3f}",
+           bits, K, bdg::size_bucket(n), ok[best].path, ok[best].col_block, ok[best].schedule, n,
+           ok[best].ms);
   bdg::append_cache_line(line);
   std::string rep = "{\"chosen\": ";
   rep += line;
-  rep += ", \"candidates\": [";
+  rep += ", \"knobs\": [\"path\", \"col_block\", \"schedule\"], \"candidates\": [";
   for (size_t i = 0; i < ok.size(); ++i) {
-    char c[128];
-    snprintf(c, sizeof c, "%s{\"path\": %d, \"col_block\": %u, \"ms\": %.3f}", i ? ", " : "",
-             ok[i].path, ok[i].col_block, ok[i].ms);
+    char c[160];
+    snprintf(c, sizeof c, "%s{\"path\": %d, \"col_block\": %u, \"schedule\": %d, \"ms\": %.3f}",
+             i ? ", " : "", ok[i].path, ok[i].col_block, ok[i].schedule, ok[i].ms);
     rep += c;
   }
   rep += "]}";
@@ -217,29 +232,51 @@ int bdg_autotune_batched(bdg_batch_plan* plan, const uint64_t* codes, uint32_t* 
   bdg::api_clear_error();
   if (!plan) return bdg::api_error(BDG_EINVAL, "plan is NULL");
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
-  const int orders[2] = {BDG_ORDER_LONGEST_FIRST, BDG_ORDER_SHARD};
-  float ms[2] = {0, 0};
+  struct Cand {
+    int order, schedule;
+    float ms;
+  };
+  std::vector<Cand> cands;
+  for (int sc = 0; sc < bdg::kTileSchedules; ++sc)
+    for (int order : {BDG_ORDER_LONGEST_FIRST, BDG_ORDER_SHARD}) cands.push_back({order, sc, 0.f});
   int st = BDG_OK;
-  for (int i = 0; i < 2 && st == BDG_OK; ++i) {
-    st = bdg_batch_plan_set_order(plan, orders[i]);
+  size_t best = 0;
+  std::vector<Cand> ok;
+  for (Cand c : cands) {
+    if (bdg_batch_plan_set_schedule(plan, c.schedule) != BDG_OK) continue;  // not built here
+    st = bdg_batch_plan_set_order(plan, c.order);
     if (st == BDG_OK)
       st = bdg::time_ms([&] { return bdg_build_knn_batched_plan(plan, codes, out_idx, out_dist,
                                                                  stream); },
-                        stream, 1, &ms[i]);
+                        stream, 1, &c.ms);
+    if (st != BDG_OK) return st;
+    ok.push_back(c);
+    if (c.ms < ok[best].ms) best = ok.size() - 1;
   }
-  if (st != BDG_OK) return st;
-  const int best = ms[0] <= ms[1] ? 0 : 1;
-  st = bdg_batch_plan_set_order(plan, orders[best]);
+  bdg::api_clear_error();
+  if (ok.empty()) return bdg::api_error(BDG_EUNSUPPORTED, "no schedule supports this plan");
+  st = bdg_batch_plan_set_schedule(plan, ok[best].schedule);
+  if (st == BDG_OK) st = bdg_batch_plan_set_order(plan, ok[best].order);
   if (st != BDG_OK) return st;
   bdg_batch_info info;
   bdg_batch_plan_info(plan, &info);
-  char line[512];
+  char line[256];
   snprintf(line, sizeof line,
            "{\"kind\": \"batched\", \"shards\": %u, \"rows\": %u, \"order\": %d, "
-           "\"ms_longest_first\": %.3f, \"ms_shard_order\": %.3f}",
-           info.shards, info.rows, orders[best], ms[0], ms[1]);
+           "\"schedule\": %d, \"ms\": %.3f}",
+           info.shards, info.rows, ok[best].order, ok[best].schedule, ok[best].ms);
   bdg::append_cache_line(line);
-  bdg::put_report(report, report_len, line);
+  std::string rep = "{\"chosen\": ";
+  rep += line;
+  rep += ", \"knobs\": [\"order\", \"schedule\"], \"candidates\": [";
+  for (size_t i = 0; i < ok.size(); ++i) {
+    char c[128];
+    snprintf(c, sizeof c, "%s{\"order\": %d, \"schedule\": %d, \"ms\": %.3f}", i ? ", " : "",
+             ok[i].order, ok[i].schedule, ok[i].ms);
+    rep += c;
+  }
+  rep += "]}";
+  bdg::put_report(report, report_len, rep);
   return BDG_OK;
 }
 

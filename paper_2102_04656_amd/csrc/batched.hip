@@ -35,6 +35,7 @@ struct bdg_batch_plan {
   uint32_t S = 0, bits = 0, words = 0, K = 0, idx_bits = 0;
   uint32_t n_total = 0, nitems = 0, grid = 0;
   int order = BDG_ORDER_LONGEST_FIRST;
+  int schedule = 0;               // tile schedule (BDG_SCHEDULE_*)
   std::vector<uint64_t> offsets;  // host copy, S + 1 entries
   void* dev = nullptr;            // items | counter | operand fragments
   size_t dev_bytes = 0;
@@ -122,6 +123,7 @@ int enqueue(const bdg_batch_plan* p, const uint64_t* codes, uint32_t* out_idx, u
     a.grid = p->grid;
     a.out_idx = out_idx;
     a.out_dist = out_dist;
+    a.schedule = p->schedule;
     e = bdg::launch_mfma_batched(a, stream);
   }
   if (e != hipSuccess) return bdg::api_device_error(e, "batched launch");
@@ -169,6 +171,12 @@ int bdg_batch_plan_create(const uint64_t* offsets, uint32_t S, uint32_t bits, ui
   p->offsets.assign(offsets, offsets + S + 1);
   p->order = (opts && opts->tile_variant == BDG_ORDER_SHARD) ? BDG_ORDER_SHARD
                                                              : BDG_ORDER_LONGEST_FIRST;
+  p->schedule = (opts && opts->struct_size >= sizeof(bdg_knn_opts)) ? (int)opts->tile_schedule : 0;
+  if (!bdg::schedule_supported(words, K, p->schedule)) {
+    const int sc = p->schedule;
+    delete p;
+    return bdg::api_error(BDG_EUNSUPPORTED, "tile schedule %d is not built for bits=%u", sc, bits);
+  }
   p->nitems = (uint32_t)make_items(p->offsets, bdg::run_rows_per_wg(K), p->order).size();
   int dev = 0, cus = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -219,6 +227,7 @@ int bdg_batch_plan_info(const bdg_batch_plan* plan, bdg_batch_info* info) {
   info->work_items = plan->nitems;
   info->workgroups = plan->grid;
   info->order = plan->order;
+  info->schedule = plan->schedule;
   uint64_t pairs = 0;
   for (uint32_t s = 0; s < plan->S; ++s) {
     const uint64_t ns = plan->offsets[s + 1] - plan->offsets[s];
@@ -236,6 +245,22 @@ int bdg_batch_plan_set_order(bdg_batch_plan* plan, int order) {
   if (order == plan->order) return BDG_OK;
   plan->order = order;
   return upload_items(plan);
+}
+
+int bdg_batch_plan_set_schedule(bdg_batch_plan* plan, int schedule) {
+  if (!plan) return bdg::api_error(BDG_EINVAL, "plan is NULL");
+  if (schedule < 0 || schedule >= bdg::kTileSchedules)
+    return bdg::api_error(BDG_EINVAL, "unknown tile schedule %d", schedule);
+  if (!bdg::schedule_supported(plan->words, plan->K, schedule))
+    return bdg::api_error(BDG_EUNSUPPORTED, "tile schedule %d is not built for bits=%u", schedule,
+                          plan->bits);
+  if (schedule == plan->schedule) return BDG_OK;
+  // a launch of the captured graph may still be queued: let it finish first
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return bdg::api_device_error(e, "synchronize");
+  plan->schedule = schedule;
+  drop_graph(plan);  // the captured launch holds the old kernel
+  return BDG_OK;
 }
 
 int bdg_build_knn_batched_plan(const bdg_batch_plan* plan, const uint64_t* codes,

@@ -19,7 +19,8 @@
 #include "kernels.h"
 
 namespace bdg {
-bool tuned_schedule(uint32_t n, uint32_t bits, uint32_t K, int* path, uint32_t* col_block);
+bool tuned_schedule(uint32_t n, uint32_t bits, uint32_t K, int* path, uint32_t* col_block,
+                    int* schedule);
 }  // namespace bdg
 
 namespace {
@@ -59,6 +60,7 @@ struct Plan {
   uint32_t words, K, n;
   uint32_t row_block, col_block, nrb, ncb;
   int path;
+  int schedule;     // matrix-core tile schedule
   bool running;     // lists carried across column blocks in the output rows
   size_t ws_bytes;  // operand fragments + sweep control words (running), or
                     // partial lists of one row block
@@ -83,10 +85,15 @@ int make_plan(uint32_t n, uint32_t bits, uint32_t K, const bdg_knn_opts* opts, P
   p->K = K;
   p->n = n;
   int path = opts ? opts->path : BDG_PATH_AUTO;
+  const bool full_opts = opts && opts->struct_size >= sizeof(bdg_knn_opts);
+  int schedule = full_opts ? (int)opts->tile_schedule : 0;
   uint32_t tuned_cb = 0;
   if (path == BDG_PATH_AUTO && !(opts && opts->col_block)) {
-    int tp = 0;
-    if (bdg::tuned_schedule(n, bits, K, &tp, &tuned_cb)) path = tp;
+    int tp = 0, ts = 0;
+    if (bdg::tuned_schedule(n, bits, K, &tp, &tuned_cb, &ts)) {
+      path = tp;
+      if (!(full_opts && opts->tile_schedule)) schedule = ts;
+    }
   }
   if (path == BDG_PATH_AUTO) path = path_auto(n, p->words, K);
   if (path != BDG_PATH_POPC && path != BDG_PATH_MFMA)
@@ -97,6 +104,9 @@ int make_plan(uint32_t n, uint32_t bits, uint32_t K, const bdg_knn_opts* opts, P
     return set_error(BDG_EUNSUPPORTED, "path %d does not support n=%u bits=%u K=%u", path, n,
                      bits, K);
   p->path = path;
+  if (path == BDG_PATH_MFMA && !bdg::schedule_supported(p->words, K, schedule))
+    return set_error(BDG_EUNSUPPORTED, "tile schedule %d is not built for bits=%u", schedule, bits);
+  p->schedule = path == BDG_PATH_MFMA ? schedule : 0;
   uint32_t cb = (opts && opts->col_block)
                     ? opts->col_block
                     : (tuned_cb ? tuned_cb
@@ -240,6 +250,7 @@ int bdg_build_knn_ex(const uint64_t* codes, uint32_t n, uint32_t bits, uint32_t 
       a.out_idx = out_idx + (size_t)r0 * K;
       a.out_dist = out_dist + (size_t)r0 * K;
       a.spin_limit = (opts && opts->struct_size >= sizeof(bdg_knn_opts)) ? opts->wait_limit : 0;
+      a.schedule = p.schedule;
       const bool timed = opts && opts->tile_events && opts->n_tile_events >= 2;
       if (timed) e = hipEventRecord(reinterpret_cast<hipEvent_t>(opts->tile_events[0]), stream);
       if (e == hipSuccess) e = bdg::launch_mfma_sweep(a, stream);

@@ -92,6 +92,11 @@ struct RunArgs {
 
 uint32_t run_idx_bits(uint32_t bits);
 bool run_supported(uint32_t n, uint32_t words, uint32_t K);
+// Tile schedules of the persistent build and the batched launch (they differ
+// in pending-buffer size and stage-ring depth, never in the result): 0 always;
+// 1 for codes of 128, 256 or 512 bits.
+constexpr int kTileSchedules = 2;
+bool schedule_supported(uint32_t words, uint32_t K, int schedule);
 uint32_t run_rows_per_wg(uint32_t K);
 // Operand prep: {0, 1} int8 fragments of every code, prep_bytes(n, words) bytes.
 size_t prep_bytes(uint32_t n, uint32_t words);
@@ -115,6 +120,7 @@ struct BatchArgs {
   uint32_t grid;           // persistent work-groups
   uint32_t* out_idx;
   uint16_t* out_dist;
+  int schedule = 0;        // tile schedule (schedule_supported)
 };
 hipError_t launch_mfma_batched(const BatchArgs& a, hipStream_t stream);
 
@@ -135,6 +141,7 @@ struct SweepArgs {
   uint32_t* out_idx;
   uint16_t* out_dist;
   uint32_t spin_limit = 0;  // polls of one dependency wait before it gives up (0: default)
+  int schedule = 0;         // tile schedule (schedule_supported)
 };
 constexpr uint32_t kSweepStallWord = 1;  // ctl[1] != 0: a dependency wait ran out
 size_t sweep_ctl_words(uint32_t nrows, uint32_t K);

@@ -86,6 +86,12 @@ bool run_supported(uint32_t n, uint32_t words, uint32_t K) {
   return mfma::run_lds_bytes(words, K) <= 160 * 1024;
 }
 
+bool schedule_supported(uint32_t words, uint32_t K, int schedule) {
+  if (schedule == 0) return true;
+  if (schedule == 1) return (words == 2 || words == 4 || words == 8) && K >= 1 && K <= 256;
+  return false;
+}
+
 size_t prep_rows(uint32_t n) {
   return (((size_t)n + 15) & ~size_t(15)) + 256;  // + at least one stage of slack
 }

@@ -17,7 +17,6 @@ namespace mfma {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void;
 
-constexpr int kBuf = 32;       // pending keys per query
 constexpr int kGroupKeys = 16; // keys one query can gain from one 16-code group
 
 // 4 bits -> 4 bytes in {0, 1}: byte t = bit t. The multiplier places copies
@@ -128,19 +127,19 @@ __device__ __forceinline__ void load_stage_wave(const v4i* __restrict__ src, v4i
   for (int i = 0; i < SV4 / 64; ++i) dma16(src + i * 64 + lane, base + i * 1024);
 }
 
-// Pending keys of one query: 4 sub-buffers of kSub slots, sub-buffer t owned
-// by the lane of lane quarter t that holds the query in the MFMA output
+// Pending keys of one query: KB slots in 4 sub-buffers of KB / 4, sub-buffer t
+// owned by the lane of lane quarter t that holds the query in the MFMA output
 // (lanes i, i + 16, i + 32, i + 48 for query i of a 16-query group), so a lane
 // appends without coordinating with the others. cq[t] = keys in sub-buffer t.
-constexpr int kSub = kBuf / 4;
 
 // Merge the pending keys of one query into its list; returns the query's new
 // threshold: the distance of the K-th key, or bits + 1 while the list is not
 // full (a candidate enters only at a distance below it).
-template <int NR>
+template <int NR, int KB>
 __device__ __forceinline__ int flush_sub(uint32_t* list_q, const uint32_t* buf_q,
                                          uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                          uint32_t K, uint32_t lane, uint32_t IB, uint32_t bits) {
+  constexpr int kBuf = KB, kSub = KB / 4;
   static_assert(kBuf <= 32 && kBuf % 4 == 0, "the pending keys of a query fit lanes 32..63");
   const uint32_t b = lane - 32u;  // slot of lane 32 + b
   const uint32_t t = b / kSub;
@@ -234,7 +233,7 @@ __device__ __forceinline__ void produce_stages(TileRing<SV4, NST>& ring, const v
 // work-group (the job's rows are split over work-groups of NW QW rows).
 // RECT: rows and columns are different code sets (no column is a row's own
 // pair), for the rectangular searches of the divide-and-conquer.
-template <int W, int NR, int QG, int GPS, int NST, bool PROD, int NW, bool RECT = false>
+template <int W, int NR, int QG, int GPS, int NST, bool PROD, int NW, int KB, bool RECT = false>
 __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
                                           const uint64_t* __restrict__ codes, uint32_t K,
                                           uint32_t bits, uint32_t IB, const TileJob& job,
@@ -246,6 +245,7 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
   constexpr int U = (QG <= 2 && GPS % (PROD ? 4 : 2) == 0) ? 2 : 1;
   constexpr int NU = GPS / U;  // units per stage
   static_assert(!PROD || NU % 2 == 0, "the producer loop keeps accumulator parity across stages");
+  constexpr int kBuf = KB, kSub = KB / 4;  // pending keys per query, per lane quarter
   constexpr int QW = 16 * QG;        // queries per wave
   constexpr int CT = 16 * GPS;       // codes per stage
   constexpr int SV4 = GPS * W * 64;  // 16-byte chunks per stage
@@ -367,7 +367,7 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
       const uint32_t i = __builtin_ctz(qm);
       qm &= qm - 1;
       const uint32_t qi = 16 * gq + i;
-      const int thr = flush_sub<NR>(
+      const int thr = flush_sub<NR, KB>(
           list_w + qi * K, buf_w + qi * kBuf, __builtin_amdgcn_readlane(csub[gq], i),
           __builtin_amdgcn_readlane(csub[gq], 16 + i), __builtin_amdgcn_readlane(csub[gq], 32 + i),
           __builtin_amdgcn_readlane(csub[gq], 48 + i), K, lane, IB, bits);
@@ -671,30 +671,38 @@ constexpr int threads_of(int W, int NR) {
 constexpr int stage_groups(int W, int NR) {
   return use_producer(W, NR) ? (W <= 4 ? 4 : 2) : (W <= 5 ? 4 : (W <= 8 ? 2 : 1));
 }
-constexpr size_t state_bytes(int K, int qg, int nw) {
-  return (size_t)nw * ((size_t)16 * qg * K + (size_t)16 * qg * kBuf + 64) * 4;
+// Schedules: every one computes the same graph. 0 = pending buffers of 32
+// keys per query; 1 = pending buffers of 16 keys per query, the LDS freed
+// going to a deeper stage ring (more stages in flight, more frequent merges).
+// Schedule 1 is built for codes of 128, 256 and 512 bits.
+constexpr int kSchedules = 2;
+constexpr int kbuf_of(int SC) { return SC == 1 ? 16 : 32; }
+constexpr bool sched_built(int W, int SC) { return SC == 0 || (W == 2 || W == 4 || W == 8); }
+constexpr size_t state_bytes(int K, int qg, int nw, int kb = 32) {
+  return (size_t)nw * ((size_t)16 * qg * K + (size_t)16 * qg * kb + 64) * 4;
 }
 // Stage slots: with a producer as many as the LDS left by lists of KC keys
 // holds (at most 8); without, the previous fixed depths. KC is the list
 // capacity class of K (kc_of): shorter lists leave room for more stages in
 // flight, which the producer needs to cover the load latency of the stream.
-constexpr int stages_of(int W, int NR, int KC) {
+constexpr int stages_of(int W, int NR, int KC, int SC = 0) {
   if (!use_producer(W, NR)) return NR == 2 ? 2 : 3;
-  const size_t avail = 160 * 1024 - state_bytes(KC, qgroups_of_nr(NR), waves_of_nr(NR)) - 256;
+  const size_t avail =
+      160 * 1024 - state_bytes(KC, qgroups_of_nr(NR), waves_of_nr(NR), kbuf_of(SC)) - 256;
   const size_t n = avail / ((size_t)stage_groups(W, NR) * W * 1024);
   return n > 8 ? 8 : (int)n;
 }
 
 // One (row block, column block) tile per launch; work-group g takes rows
 // [R g, R g + R) of the row block, R = NW QW.
-template <int W, int NR, int QG, int GPS, int NST, bool RECT = false>
+template <int W, int NR, int QG, int GPS, int NST, int KB, bool RECT = false>
 __global__ __launch_bounds__(threads_of(W, NR), 1) void knn_mfma_run_kernel(
     const v4i* __restrict__ frags, const uint64_t* __restrict__ codes, uint32_t K, uint32_t bits,
     uint32_t IB, TileJob job) {
   __shared__ TileRing<GPS * W * 64, NST> ring;
   extern __shared__ uint32_t state[];
   constexpr int NW = waves_of_nr(NR);
-  tile_body<W, NR, QG, GPS, NST, use_producer(W, NR), NW, RECT>(
+  tile_body<W, NR, QG, GPS, NST, use_producer(W, NR), NW, KB, RECT>(
       frags, codes, K, bits, IB, job, blockIdx.x * (NW * 16 * QG), ring, state);
 }
 
@@ -702,7 +710,7 @@ __global__ __launch_bounds__(threads_of(W, NR), 1) void knn_mfma_run_kernel(
 // takes work items (one shard's 4 QW rows against all the shard's columns)
 // from a shared counter until the list is exhausted. Items are ordered
 // longest first, so the uneven shards balance over the CUs.
-template <int W, int NR, int QG, int GPS, int NST>
+template <int W, int NR, int QG, int GPS, int NST, int KB>
 __global__ __launch_bounds__(threads_of(W, NR), 1) void knn_mfma_batched_kernel(
     const v4i* __restrict__ frags, const uint64_t* __restrict__ codes, uint32_t K, uint32_t bits,
     uint32_t IB, const BatchItem* __restrict__ items, uint32_t nitems, uint32_t* counter,
@@ -726,8 +734,8 @@ __global__ __launch_bounds__(threads_of(W, NR), 1) void knn_mfma_batched_kernel(
     job.fresh = 1;
     job.out_idx = out_idx + (size_t)b.row0 * K;
     job.out_dist = out_dist + (size_t)b.row0 * K;
-    tile_body<W, NR, QG, GPS, NST, use_producer(W, NR), waves_of_nr(NR)>(frags, codes, K, bits, IB,
-                                                                         job, 0, ring, state);
+    tile_body<W, NR, QG, GPS, NST, use_producer(W, NR), waves_of_nr(NR), KB>(
+        frags, codes, K, bits, IB, job, 0, ring, state);
   }
 }
 
@@ -747,7 +755,7 @@ constexpr uint32_t kSweepSpinLimit = 1u << 23;
 // wrote: it waits for progress[t] = c. That item was claimed earlier, by a
 // work-group already running, and its own wait is on a still earlier item,
 // down to a first-block item that waits for nothing, so every wait ends.
-template <int W, int NR, int QG, int GPS, int NST>
+template <int W, int NR, int QG, int GPS, int NST, int KB>
 __global__ __launch_bounds__(threads_of(W, NR), 1) void knn_mfma_sweep_kernel(
     const v4i* __restrict__ frags, const uint64_t* __restrict__ codes, uint32_t K, uint32_t bits,
     uint32_t IB, uint32_t row0, uint32_t nrows, uint32_t ncols, uint32_t col_block,
@@ -790,8 +798,8 @@ __global__ __launch_bounds__(threads_of(W, NR), 1) void knn_mfma_sweep_kernel(
     job.fresh = c == 0;
     job.out_idx = out_idx + (size_t)t * RT * K;
     job.out_dist = out_dist + (size_t)t * RT * K;
-    tile_body<W, NR, QG, GPS, NST, use_producer(W, NR), waves_of_nr(NR)>(frags, codes, K, bits, IB,
-                                                                         job, 0, ring, state);
+    tile_body<W, NR, QG, GPS, NST, use_producer(W, NR), waves_of_nr(NR), KB>(
+        frags, codes, K, bits, IB, job, 0, ring, state);
     // the tile's lists are in the output rows: publish them
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
@@ -817,7 +825,9 @@ inline int kc_of(uint32_t K) {
 inline int qg_of(uint32_t K) { return qgroups_of_nr(nr_of(K)); }
 inline int nw_of(uint32_t K) { return waves_of_nr(nr_of(K)); }
 
-inline size_t run_state_bytes(uint32_t K, int qg) { return state_bytes((int)K, qg, nw_of(K)); }
+inline size_t run_state_bytes(uint32_t K, int qg, int kb = 32) {
+  return state_bytes((int)K, qg, nw_of(K), kb);
+}
 
 inline size_t run_lds_bytes(uint32_t W, uint32_t K) {
   const size_t stage = (size_t)stage_groups((int)W, nr_of(K)) * W * 1024;
@@ -831,10 +841,10 @@ inline hipError_t launch_run_w(const RunArgs& a, hipStream_t stream) {
   constexpr int NST = stages_of(W, NR, KC);
   static_assert(NST >= 2, "stage ring needs two slots");
   // the rectangular variant exists for lists of up to 64 keys only
-  auto kern = knn_mfma_run_kernel<W, NR, QG, GPS, NST>;
+  auto kern = knn_mfma_run_kernel<W, NR, QG, GPS, NST, 32>;
   if (a.rect) {
     if constexpr (NR == 1)
-      kern = knn_mfma_run_kernel<W, NR, QG, GPS, NST, true>;
+      kern = knn_mfma_run_kernel<W, NR, QG, GPS, NST, 32, true>;
     else
       return hipErrorInvalidValue;
   }
@@ -858,14 +868,14 @@ inline hipError_t launch_run_w(const RunArgs& a, hipStream_t stream) {
   return hipGetLastError();
 }
 
-template <int W, int NR, int KC>
+template <int W, int NR, int KC, int SC>
 inline hipError_t launch_batched_w(const BatchArgs& a, hipStream_t stream) {
   constexpr int QG = qgroups_of_nr(NR);
   constexpr int GPS = stage_groups(W, NR);
-  constexpr int NST = stages_of(W, NR, KC);
+  constexpr int NST = stages_of(W, NR, KC, SC);
   static_assert(NST >= 2, "stage ring needs two slots");
-  auto kern = knn_mfma_batched_kernel<W, NR, QG, GPS, NST>;
-  const size_t lds = run_state_bytes(a.K, QG);
+  auto kern = knn_mfma_batched_kernel<W, NR, QG, GPS, NST, kbuf_of(SC)>;
+  const size_t lds = run_state_bytes(a.K, QG, kbuf_of(SC));
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -876,14 +886,14 @@ inline hipError_t launch_batched_w(const BatchArgs& a, hipStream_t stream) {
   return hipGetLastError();
 }
 
-template <int W, int NR, int KC>
+template <int W, int NR, int KC, int SC>
 inline hipError_t launch_sweep_w(const SweepArgs& a, hipStream_t stream) {
   constexpr int QG = qgroups_of_nr(NR);
   constexpr int GPS = stage_groups(W, NR);
-  constexpr int NST = stages_of(W, NR, KC);
+  constexpr int NST = stages_of(W, NR, KC, SC);
   static_assert(NST >= 2, "stage ring needs two slots");
-  auto kern = knn_mfma_sweep_kernel<W, NR, QG, GPS, NST>;
-  const size_t lds = run_state_bytes(a.K, QG);
+  auto kern = knn_mfma_sweep_kernel<W, NR, QG, GPS, NST, kbuf_of(SC)>;
+  const size_t lds = run_state_bytes(a.K, QG, kbuf_of(SC));
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -903,26 +913,44 @@ inline hipError_t launch_sweep_w(const SweepArgs& a, hipStream_t stream) {
   return hipGetLastError();
 }
 
+template <int W, int SC>
+inline hipError_t launch_sweep_sc(const SweepArgs& a, hipStream_t stream) {
+  switch (kc_of(a.K)) {
+    case 32: return launch_sweep_w<W, 1, 32, SC>(a, stream);
+    case 64: return launch_sweep_w<W, 1, 64, SC>(a, stream);
+    case 112: return launch_sweep_w<W, 2, 112, SC>(a, stream);
+    case 128: return launch_sweep_w<W, 2, 128, SC>(a, stream);
+    default: return launch_sweep_w<W, 4, 256, SC>(a, stream);
+  }
+}
+
 template <int W>
 inline hipError_t launch_sweep_nr(const SweepArgs& a, hipStream_t stream) {
+  if (a.schedule == 1) {
+    if constexpr (sched_built(W, 1)) return launch_sweep_sc<W, 1>(a, stream);
+    return hipErrorInvalidValue;
+  }
+  return a.schedule == 0 ? launch_sweep_sc<W, 0>(a, stream) : hipErrorInvalidValue;
+}
+
+template <int W, int SC>
+inline hipError_t launch_batched_sc(const BatchArgs& a, hipStream_t stream) {
   switch (kc_of(a.K)) {
-    case 32: return launch_sweep_w<W, 1, 32>(a, stream);
-    case 64: return launch_sweep_w<W, 1, 64>(a, stream);
-    case 112: return launch_sweep_w<W, 2, 112>(a, stream);
-    case 128: return launch_sweep_w<W, 2, 128>(a, stream);
-    default: return launch_sweep_w<W, 4, 256>(a, stream);
+    case 32: return launch_batched_w<W, 1, 32, SC>(a, stream);
+    case 64: return launch_batched_w<W, 1, 64, SC>(a, stream);
+    case 112: return launch_batched_w<W, 2, 112, SC>(a, stream);
+    case 128: return launch_batched_w<W, 2, 128, SC>(a, stream);
+    default: return launch_batched_w<W, 4, 256, SC>(a, stream);
   }
 }
 
 template <int W>
 inline hipError_t launch_batched_nr(const BatchArgs& a, hipStream_t stream) {
-  switch (kc_of(a.K)) {
-    case 32: return launch_batched_w<W, 1, 32>(a, stream);
-    case 64: return launch_batched_w<W, 1, 64>(a, stream);
-    case 112: return launch_batched_w<W, 2, 112>(a, stream);
-    case 128: return launch_batched_w<W, 2, 128>(a, stream);
-    default: return launch_batched_w<W, 4, 256>(a, stream);
+  if (a.schedule == 1) {
+    if constexpr (sched_built(W, 1)) return launch_batched_sc<W, 1>(a, stream);
+    return hipErrorInvalidValue;
   }
+  return a.schedule == 0 ? launch_batched_sc<W, 0>(a, stream) : hipErrorInvalidValue;
 }
 
 template <int W>

@@ -149,3 +149,13 @@ def test_build_check_validates_before_touching_the_gpu():
     o = bdg.make_opts(path=bdg.PATH_POPC)
     assert L.bdg_build_knn_check(1000, 256, 16, ctypes.byref(o), None) == bdg.BDG_OK
     assert L.bdg_build_knn_check(0, 256, 16, None, None) == bdg.BDG_OK
+
+
+def test_schedule_validation():
+    L = bdg.lib()
+    # schedule 1 is built for 128, 256 and 512 bits only; unknown schedules
+    o = bdg.make_opts(path=bdg.PATH_MFMA, tile_schedule=1)
+    assert call_ex(bits=192, opts=o) == bdg.BDG_EUNSUPPORTED
+    o = bdg.make_opts(path=bdg.PATH_MFMA, tile_schedule=7)
+    assert call_ex(bits=256, opts=o) == bdg.BDG_EUNSUPPORTED
+    assert L.bdg_batch_plan_set_schedule(None, 1) == bdg.BDG_EINVAL

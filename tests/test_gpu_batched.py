@@ -113,8 +113,22 @@ def test_orders_graph_replay_and_autotune_agree():
         stream.synchronize()
         got = to_np(out)
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), f"replay {rep}"
+    # the deep-ring schedule builds the same graph, eagerly and through a graph
+    plan.set_order(bdg.ORDER_LONGEST_FIRST)
+    plan.set_schedule(bdg.SCHEDULE_DEEP_RING)
+    assert plan.info().schedule == bdg.SCHEDULE_DEEP_RING
+    got = to_np(plan.build(d))
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+    out[0].zero_()
+    torch.cuda.synchronize()
+    plan.build(d, out=out, stream=stream, graph=True)
+    stream.synchronize()
+    got = to_np(out)
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
     report = plan.autotune(d)
-    assert '"kind": "batched"' in report
+    assert '"kind": "batched"' in report and '"schedule"' in report
+    import json
+    assert len(json.loads(report)["candidates"]) == 4
     got = to_np(plan.build(d))
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
     plan.close()
@@ -214,6 +228,18 @@ def test_autotune_build_keeps_the_graph():
     opts, report = bdg.autotune_build(d, 32)
     assert opts.path in (bdg.PATH_MFMA, bdg.PATH_POPC) and opts.col_block > 0
     assert '"chosen"' in report
+    import json
+    rep = json.loads(report)
+    assert rep["knobs"] == ["path", "col_block", "schedule"]
+    cands = rep["candidates"]
+    assert {c["schedule"] for c in cands} == {0, 1} and len(cands) >= 3
+    rows = np.arange(0, 20_000, 97)
+    # every candidate schedule the tuner timed builds the same graph
+    for c in cands:
+        print(f"[autotune] candidate {c}", flush=True)
+        ci, cd = to_np(bdg.build_knn(d, 32, path=c["path"], col_block=c["col_block"],
+                                     schedule=c["schedule"]))
+        assert np.array_equal(ci[rows], want[0]) and np.array_equal(cd[rows], want[1]), c
     idx, dist = bdg.build_knn(d, 32, path=opts.path, col_block=opts.col_block)
     gi, gd = to_np((idx, dist))
     rows = np.arange(0, 20_000, 97)
