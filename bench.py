@@ -128,7 +128,7 @@ class HipEvents:
             self.rt.hipEventDestroy(h)
 
 
-def run_path(codes_dev, n, bits, K, path, row_block, col_block, steps, warmup):
+def run_path(codes_dev, n, bits, K, path, row_block, col_block, steps, warmup, schedule=0):
     """Time `steps` full builds; returns (ms/step, tile kernel stats, outputs).
 
     The distance-tile launches of one build are, in order: one per row block
@@ -149,13 +149,14 @@ def run_path(codes_dev, n, bits, K, path, row_block, col_block, steps, warmup):
     stream = torch.cuda.current_stream()
     ev = HipEvents(2 * nl * steps)
     # workspace allocated once, outside the timed region
-    o = bdg.make_opts(path=path, row_block=row_block, col_block=col_block)
+    o = bdg.make_opts(path=path, row_block=row_block, col_block=col_block, tile_schedule=schedule)
     ws_bytes = bdg.bdg_build_knn_workspace_size(n, bits, K, o)
     ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device="cuda")
 
     def step(s):
         op = bdg.make_opts(path=path, row_block=row_block, col_block=col_block,
-                           workspace=ws.data_ptr(), workspace_bytes=ws_bytes)
+                           tile_schedule=schedule, workspace=ws.data_ptr(),
+                           workspace_bytes=ws_bytes)
         if s is not None:
             op.n_tile_events = 2 * nl
             op.tile_events = ev.slice_ptr(2 * nl * s)
@@ -175,7 +176,7 @@ def run_path(codes_dev, n, bits, K, path, row_block, col_block, steps, warmup):
     # outcome of the last build on this workspace: the persistent launch's
     # stall flag (never set in a correct run)
     chk = bdg.make_opts(path=path, row_block=row_block, col_block=col_block,
-                        workspace=ws.data_ptr(), workspace_bytes=ws_bytes)
+                        tile_schedule=schedule, workspace=ws.data_ptr(), workspace_bytes=ws_bytes)
     stall = bdg.bdg_build_knn_check(n, bits, K, chk, stream)
     if stall != 0:
         raise RuntimeError(f"bdg_build_knn_check: {stall} {bdg.last_error()}")
@@ -428,11 +429,12 @@ def batched_popc_leg(d, offsets, sizes, bits, K, pairs, out, stream):
     same = bool(torch.equal(pi, out[0]) and torch.equal(pd, out[1]))
     ops = pairs * 2 * bits // 32
     log(f"[bench] vector-ALU path: {ms:.1f} ms, graph identical to the batched launch: {same}")
+    peak = MEASURED_PEAKS.get("valu_int32", PEAK_VALU_TOPS)
     return {"value": pairs / (ms * 1e-3), "ms_per_step": ms, "steps": 1,
             "kernel": "knn_popc_kernel + merge_lists_kernel, one bdg_build_knn_ex per shard",
-            "achieved": ops / (ms * 1e-3) / 1e12, "peak": PEAK_VALU_TOPS, "unit": "T ops/s",
-            "frac": ops / (ms * 1e-3) / 1e12 / PEAK_VALU_TOPS, "timing": "end to end, host clock",
-            "identical_to_batched_graph": same}
+            "achieved": ops / (ms * 1e-3) / 1e12, "peak": peak, "unit": "T ops/s",
+            "frac": ops / (ms * 1e-3) / 1e12 / peak, "peak_derived": PEAK_VALU_TOPS,
+            "timing": "end to end, host clock", "identical_to_batched_graph": same}
 
 
 def bench_batched(args, w):
@@ -446,6 +448,7 @@ def bench_batched(args, w):
                                            c_lo=w["c_lo"], c_hi=w["c_hi"], bits=w["bits"],
                                            p=w["p"], seed=w["seed"])
     bits, K = w["bits"], w["K"]
+    peaks = measure_peaks()
     sizes = np.diff(offsets.astype(np.int64))
     pairs = int((sizes * (sizes - 1)).sum())
     log(f"[bench] generated {int(offsets[-1])} rows in {time.perf_counter() - t0:.1f}s; "
@@ -490,7 +493,9 @@ def bench_batched(args, w):
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_INT8_TOPS,
                      "unit": "TOP/s", "frac": achieved / PEAK_INT8_TOPS, "traffic": None,
                      "kernel": "knn_mfma_batched_kernel", "kernel_avg_ms": launch_ms,
-                     "ops_per_pair": 2 * bits, "pairs_per_launch": pairs},
+                     "ops_per_pair": 2 * bits, "pairs_per_launch": pairs,
+                     "sustained_probe": peaks["mfma_int8"]},
+        "measured_peaks_tops": peaks,
     }
     rec = recorded_traffic("knn_mfma_batched_kernel", args.workload)
     if rec is not None:
@@ -528,10 +533,27 @@ def bench_batched(args, w):
     plan.close()
 
 
-def time_build(w, workload, path, steps, warmup, other_steps, other_warmup, other_path):
+MEASURED_PEAKS = {}  # filled by main(): sustained rates from bdg_probe_peak, T ops/s
+
+
+def measure_peaks():
+    """Sustained rates of the two units (bdg_probe_peak), T ops/s: 32-bit
+    integer vector instructions and int8 matrix-core operations on the tile's
+    operand bytes."""
+    from paper_2102_04656_amd import bdg
+    MEASURED_PEAKS["valu_int32"] = bdg.probe_peak(bdg.PEAK_VALU_INT32) / 1e12
+    MEASURED_PEAKS["mfma_int8"] = bdg.probe_peak(bdg.PEAK_MFMA_INT8) / 1e12
+    log(f"[bench] measured peaks (T ops/s): {MEASURED_PEAKS}")
+    return dict(MEASURED_PEAKS)
+
+
+def time_build(w, workload, path, steps, warmup, other_steps, other_warmup, other_path,
+               autotune=False):
     """Generate one single-partition workload, time its build on `path` (and
     the other distance path for `other_steps`), return (codes, codes_dev,
-    outputs of the main path, result fields)."""
+    outputs of the main path, result fields). With `autotune` the schedule
+    (path, column block, tile schedule) is first tuned by bdg_autotune_build,
+    outside the timed region, and the timed builds take the winner."""
     import torch
     from paper_2102_04656_amd import bdg, datagen
     n, bits, K = w["n"], w["bits"], w["K"]
@@ -544,12 +566,24 @@ def time_build(w, workload, path, steps, warmup, other_steps, other_warmup, othe
     torch.cuda.synchronize()
 
     paths = {"mfma": bdg.PATH_MFMA, "popc": bdg.PATH_POPC}
+    schedule, tuned = 0, None
+    if autotune:
+        log(f"[bench] {workload}: autotuning the build schedule")
+        t0 = time.perf_counter()
+        o, rep = bdg.autotune_build(codes_dev, K, bits=bits, row_block=row_block)
+        torch.cuda.synchronize()
+        tuned = json.loads(rep)
+        tuned["tuning_s"] = time.perf_counter() - t0
+        log(f"[bench] autotune ({tuned['tuning_s']:.1f} s): {rep}")
+        path = {bdg.PATH_MFMA: "mfma", bdg.PATH_POPC: "popc"}[o.path]
+        col_block, schedule = o.col_block, o.tile_schedule
     runs, outs = {}, None
     order = [path] + ([p for p in paths if p != path] if other_path else [])
     for name in order:
         st, wu = (steps, warmup) if name == path else (other_steps, other_warmup)
         log(f"[bench] {workload}: timing path {name}: {st} steps after {wu} warmup")
-        ms, kern, out = run_path(codes_dev, n, bits, K, paths[name], row_block, col_block, st, wu)
+        ms, kern, out = run_path(codes_dev, n, bits, K, paths[name], row_block, col_block, st, wu,
+                                 schedule if name == path else 0)
         runs[name] = dict(ms_per_step=ms, kernel=kern, steps=st)
         if name == path:
             outs = out
@@ -565,12 +599,21 @@ def time_build(w, workload, path, steps, warmup, other_steps, other_warmup, othe
         if name == "mfma":
             ops_pair, peak, bound, kname = 2 * bits, PEAK_INT8_TOPS, "mfma", "knn_mfma_sweep_kernel"
         else:
-            ops_pair, peak, bound, kname = 2 * bits // 32, PEAK_VALU_TOPS, "alu", "knn_popc_kernel"
+            # the vector-ALU peak is the measured one (bdg_probe_peak); the
+            # derivation from unit counts and clock is reported beside it
+            ops_pair, bound, kname = 2 * bits // 32, "alu", "knn_popc_kernel"
+            peak = MEASURED_PEAKS.get("valu_int32", PEAK_VALU_TOPS)
         achieved = kern["pairs_per_launch"] * ops_pair / (kern["avg_ms"] * 1e-3) / 1e12
         r = {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TOP/s",
              "frac": achieved / peak, "traffic": None, "kernel": kname,
              "kernel_avg_ms": kern["avg_ms"], "ops_per_pair": ops_pair,
              "pairs_per_launch": kern["pairs_per_launch"]}
+        if name == "mfma" and "mfma_int8" in MEASURED_PEAKS:
+            r["sustained_probe"] = MEASURED_PEAKS["mfma_int8"]
+            r["frac_of_probe"] = achieved / MEASURED_PEAKS["mfma_int8"]
+        if name != "mfma":
+            r["peak_source"] = "measured (bdg_probe_peak, XOR + popcount-accumulate + add)"
+            r["peak_derived"] = PEAK_VALU_TOPS
         rec = recorded_traffic(kname, workload)
         if rec is not None:
             r["traffic"] = rec["bytes_per_launch"]
@@ -583,8 +626,11 @@ def time_build(w, workload, path, steps, warmup, other_steps, other_warmup, othe
            "dtype": "i8" if path == "mfma" else "u32",
            "config": {"workload": workload, "n": n, "bits": bits, "K": K,
                       "row_block": row_block, "col_block": col_block, "path": path,
+                      "tile_schedule": schedule,
                       "centres": w["n_centres"], "flip_p": w["p"], "seed": w["seed"]},
            "roofline": roof(path), "stall": runs[path]["kernel"]["stall"]}
+    if tuned is not None:
+        res["autotune"] = tuned
     for name, r in runs.items():
         if name != path:
             rr = roof(name)
@@ -593,6 +639,9 @@ def time_build(w, workload, path, steps, warmup, other_steps, other_warmup, othe
                                    "kernel_avg_ms": r["kernel"]["avg_ms"],
                                    "achieved": rr["achieved"], "peak": rr["peak"],
                                    "frac": rr["frac"], "stall": r["kernel"]["stall"]}
+            for key in ("peak_source", "peak_derived"):
+                if key in rr:
+                    res[f"{name}_path"][key] = rr[key]
     return codes, codes_dev, outs, res
 
 
@@ -614,6 +663,9 @@ def main():
     ap.add_argument("--other-warmup", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the build schedule (bdg_autotune_build) before the timed builds, "
+                         "outside the timed region, and time the winner")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed builds, run a streaming kernel of known size "
                          "(for scaling hardware byte counters)")
@@ -641,8 +693,10 @@ def main():
     if "n_shards" in w:
         return bench_batched(args, w)
     main_path = "mfma" if args.path == "auto" else args.path
+    peaks = measure_peaks()
     codes, codes_dev, outs, res = time_build(w, args.workload, main_path, args.steps, args.warmup,
-                                             args.other_steps, args.other_warmup, args.other_path)
+                                             args.other_steps, args.other_warmup, args.other_path,
+                                             autotune=args.autotune)
     n, bits, K = w["n"], w["bits"], w["K"]
     result = {
         "metric": METRIC,
@@ -659,6 +713,7 @@ def main():
         "data": "synthetic",
     }
     result.update(res)
+    result["measured_peaks_tops"] = peaks
     if args.copy_calibration:
         copy_calibration()
     if not args.no_cpu_baseline:
@@ -688,7 +743,7 @@ def main():
     if args.secondary != "none" and args.secondary != args.workload:
         w2 = datagen.WORKLOADS[args.secondary]
         _, _, o2, r2 = time_build(w2, args.secondary, "mfma", args.steps, args.warmup, 0, 0,
-                                  other_path=False)
+                                  other_path=False, autotune=args.autotune)
         del o2
         result["secondary"] = r2
     if args.recall:

@@ -473,6 +473,21 @@ int bdg_autotune_batched(bdg_batch_plan *plan, const uint64_t *codes, uint32_t *
 
 /* ------------------------------------------------------------ diagnostics --- */
 
+/*
+ * Sustained rate of one execution unit, for the roofline denominators of the
+ * two Hamming tiles (not part of the method): a fixed loop of independent
+ * instructions over every CU, timed with events on `stream` after a warm-up
+ * run; waits for completion. BDG_PEAK_VALU_INT32: 32-bit integer vector
+ * instructions per second (XOR, popcount-accumulate, add; lane operations).
+ * BDG_PEAK_MFMA_INT8: int8 matrix-core operations per second (2 per
+ * multiply-accumulate) of v_mfma_i32_16x16x64_i8 on random {0, 1} x +-1
+ * operand bytes, the matrix tile's operands. Errors: BDG_EINVAL (unit,
+ * NULL), BDG_ENOMEM, BDG_EDEVICE.
+ */
+#define BDG_PEAK_VALU_INT32 0
+#define BDG_PEAK_MFMA_INT8 1
+int bdg_probe_peak(int unit, double *ops_per_second, void *stream);
+
 const char *bdg_status_string(int status);
 /* Message of the last failed call on this thread ("" if none). */
 const char *bdg_last_error(void);

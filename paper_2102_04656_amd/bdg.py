@@ -118,6 +118,7 @@ _SIGS = {
     "bdg_build_knn_workspace_size": [_u32, _u32, _u32, _p, _p],
     "bdg_build_knn_check": [_u32, _u32, _u32, _p, _p],
     "bdg_build_knn_noalloc": [_p, _u32, _u32, _u32, _p, _p, _p],
+    "bdg_probe_peak": [ctypes.c_int, _p, _p],
     "bdg_merge_lists": [_p, _p, _u32, _u32, _u32, _u32, _p, _p, _p],
     "bdg_propagate": [_p, _u32, _u32, _u32, _p, _p, _p, _p],
     "bdg_bkmeans": [_p, _u32, _u32, _p, _u32, _p, _u32, _u32, _p, _p],
@@ -224,6 +225,16 @@ def bdg_build_knn_noalloc(codes, n, bits, K, out_idx, out_dist, stream=None) -> 
     nothing; inputs up to the static scratch size)."""
     return lib().bdg_build_knn_noalloc(_ptr(codes), n, bits, K, _ptr(out_idx), _ptr(out_dist),
                                        _stream(stream))
+
+
+PEAK_VALU_INT32, PEAK_MFMA_INT8 = 0, 1
+
+
+def probe_peak(unit: int, stream=None) -> float:
+    """Measured sustained rate of a unit (operations per second)."""
+    v = ctypes.c_double()
+    _check(lib().bdg_probe_peak(unit, ctypes.byref(v), _stream(stream)))
+    return v.value
 
 
 def bdg_build_knn_workspace_size(n, bits, K, opts=None) -> int:

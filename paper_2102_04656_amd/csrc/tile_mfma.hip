@@ -33,10 +33,11 @@
 // the stages and publishes a count of landed ones; otherwise the compute waves
 // claim and copy stages themselves.
 //
-// Filter. The accumulator starts at the per-query bias thr - popc(q), so after
-// the contraction acc = thr - ham: a candidate can enter the list only if
-// acc > 0. The common case (no candidate of a 16-code group beats any of the
-// wave's thresholds) costs a max-reduction and one compare per group.
+// Filter. The accumulators start at zero, so after the contraction
+// acc = popc(q) - ham; adding the per-query bias thr - popc(q) gives thr - ham,
+// and a candidate can enter the list only if that is positive. The common case
+// (no candidate of a 16-code group beats any of the wave's thresholds) costs a
+// max-reduction and one compare per group.
 //
 // Lists. Keys are dist << IB | column (global column index, IB = 32 - bits
 // needed for a distance), so key order is the (distance, index) order of the

@@ -159,3 +159,11 @@ def test_schedule_validation():
     o = bdg.make_opts(path=bdg.PATH_MFMA, tile_schedule=7)
     assert call_ex(bits=256, opts=o) == bdg.BDG_EUNSUPPORTED
     assert L.bdg_batch_plan_set_schedule(None, 1) == bdg.BDG_EINVAL
+
+
+def test_probe_peak_validates_before_touching_the_gpu():
+    L = bdg.lib()
+    rate = ctypes.c_double(0)
+    assert L.bdg_probe_peak(5, ctypes.byref(rate), None) == bdg.BDG_EINVAL
+    assert "unknown unit" in bdg.last_error()
+    assert L.bdg_probe_peak(bdg.PEAK_VALU_INT32, None, None) == bdg.BDG_EINVAL
