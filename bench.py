@@ -128,7 +128,8 @@ class HipEvents:
             self.rt.hipEventDestroy(h)
 
 
-def run_path(codes_dev, n, bits, K, path, row_block, col_block, steps, warmup, schedule=0):
+def run_path(codes_dev, n, bits, K, path, row_block, col_block, steps, warmup, schedule=0,
+             bound_group=0):
     """Time `steps` full builds; returns (ms/step, tile kernel stats, outputs).
 
     The distance-tile launches of one build are, in order: one per row block
@@ -149,14 +150,15 @@ def run_path(codes_dev, n, bits, K, path, row_block, col_block, steps, warmup, s
     stream = torch.cuda.current_stream()
     ev = HipEvents(2 * nl * steps)
     # workspace allocated once, outside the timed region
-    o = bdg.make_opts(path=path, row_block=row_block, col_block=col_block, tile_schedule=schedule)
+    o = bdg.make_opts(path=path, row_block=row_block, col_block=col_block, tile_schedule=schedule,
+                      bound_group=bound_group)
     ws_bytes = bdg.bdg_build_knn_workspace_size(n, bits, K, o)
     ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device="cuda")
 
     def step(s):
         op = bdg.make_opts(path=path, row_block=row_block, col_block=col_block,
-                           tile_schedule=schedule, workspace=ws.data_ptr(),
-                           workspace_bytes=ws_bytes)
+                           tile_schedule=schedule, bound_group=bound_group,
+                           workspace=ws.data_ptr(), workspace_bytes=ws_bytes)
         if s is not None:
             op.n_tile_events = 2 * nl
             op.tile_events = ev.slice_ptr(2 * nl * s)
@@ -176,7 +178,8 @@ def run_path(codes_dev, n, bits, K, path, row_block, col_block, steps, warmup, s
     # outcome of the last build on this workspace: the persistent launch's
     # stall flag (never set in a correct run)
     chk = bdg.make_opts(path=path, row_block=row_block, col_block=col_block,
-                        tile_schedule=schedule, workspace=ws.data_ptr(), workspace_bytes=ws_bytes)
+                        tile_schedule=schedule, bound_group=bound_group,
+                        workspace=ws.data_ptr(), workspace_bytes=ws_bytes)
     stall = bdg.bdg_build_knn_check(n, bits, K, chk, stream)
     if stall != 0:
         raise RuntimeError(f"bdg_build_knn_check: {stall} {bdg.last_error()}")
@@ -454,7 +457,7 @@ def bench_batched(args, w):
     log(f"[bench] generated {int(offsets[-1])} rows in {time.perf_counter() - t0:.1f}s; "
         f"{pairs:.4g} pairs")
     d = torch.from_numpy(codes.view(np.int64)).cuda()
-    plan = bdg.BatchPlan(offsets, bits, K)
+    plan = bdg.BatchPlan(offsets, bits, K, bound_group=args.bound_group)
     out = plan.outputs()
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
@@ -489,7 +492,9 @@ def bench_batched(args, w):
                    "rows": int(offsets[-1]), "bits": bits, "K": K, "pairs": pairs,
                    "work_items": info.work_items, "workgroups": info.workgroups,
                    "order": "longest-first" if info.order == 0 else "shard",
-                   "launch": "hip-graph"},
+                   "schedule": info.schedule, "bound_group": info.bound_group,
+                   "launch": "hip-graph (operand prep, admission bounds, persistent kernel; "
+                             "kernel_avg_ms times the whole replay)"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_INT8_TOPS,
                      "unit": "TOP/s", "frac": achieved / PEAK_INT8_TOPS, "traffic": None,
                      "kernel": "knn_mfma_batched_kernel", "kernel_avg_ms": launch_ms,
@@ -548,7 +553,7 @@ def measure_peaks():
 
 
 def time_build(w, workload, path, steps, warmup, other_steps, other_warmup, other_path,
-               autotune=False):
+               autotune=False, bound_group=0):
     """Generate one single-partition workload, time its build on `path` (and
     the other distance path for `other_steps`), return (codes, codes_dev,
     outputs of the main path, result fields). With `autotune` the schedule
@@ -576,14 +581,15 @@ def time_build(w, workload, path, steps, warmup, other_steps, other_warmup, othe
         tuned["tuning_s"] = time.perf_counter() - t0
         log(f"[bench] autotune ({tuned['tuning_s']:.1f} s): {rep}")
         path = {bdg.PATH_MFMA: "mfma", bdg.PATH_POPC: "popc"}[o.path]
-        col_block, schedule = o.col_block, o.tile_schedule
+        col_block, schedule, bound_group = o.col_block, o.tile_schedule, o.bound_group
     runs, outs = {}, None
     order = [path] + ([p for p in paths if p != path] if other_path else [])
     for name in order:
         st, wu = (steps, warmup) if name == path else (other_steps, other_warmup)
         log(f"[bench] {workload}: timing path {name}: {st} steps after {wu} warmup")
         ms, kern, out = run_path(codes_dev, n, bits, K, paths[name], row_block, col_block, st, wu,
-                                 schedule if name == path else 0)
+                                 schedule if name == path else 0,
+                                 bound_group if name == path else 0)
         runs[name] = dict(ms_per_step=ms, kernel=kern, steps=st)
         if name == path:
             outs = out
@@ -627,6 +633,7 @@ def time_build(w, workload, path, steps, warmup, other_steps, other_warmup, othe
            "config": {"workload": workload, "n": n, "bits": bits, "K": K,
                       "row_block": row_block, "col_block": col_block, "path": path,
                       "tile_schedule": schedule,
+                      "bound_group": bound_group or bdg.BOUND_GROUP_DEFAULT,
                       "centres": w["n_centres"], "flip_p": w["p"], "seed": w["seed"]},
            "roofline": roof(path), "stall": runs[path]["kernel"]["stall"]}
     if tuned is not None:
@@ -663,6 +670,9 @@ def main():
     ap.add_argument("--other-warmup", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--bound-group", type=int, default=0,
+                    help="admission bounds of the matrix-core build: rows per pivot group "
+                         "(0: the library default, 1: off)")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the build schedule (bdg_autotune_build) before the timed builds, "
                          "outside the timed region, and time the winner")
@@ -696,7 +706,7 @@ def main():
     peaks = measure_peaks()
     codes, codes_dev, outs, res = time_build(w, args.workload, main_path, args.steps, args.warmup,
                                              args.other_steps, args.other_warmup, args.other_path,
-                                             autotune=args.autotune)
+                                             autotune=args.autotune, bound_group=args.bound_group)
     n, bits, K = w["n"], w["bits"], w["K"]
     result = {
         "metric": METRIC,
@@ -743,7 +753,8 @@ def main():
     if args.secondary != "none" and args.secondary != args.workload:
         w2 = datagen.WORKLOADS[args.secondary]
         _, _, o2, r2 = time_build(w2, args.secondary, "mfma", args.steps, args.warmup, 0, 0,
-                                  other_path=False, autotune=args.autotune)
+                                  other_path=False, autotune=args.autotune,
+                                  bound_group=args.bound_group)
         del o2
         result["secondary"] = r2
     if args.recall:

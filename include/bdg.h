@@ -96,8 +96,31 @@ typedef struct bdg_knn_opts {
                                 graph is the same under every schedule);
                                 default 0, or the autotuned one with path AUTO
                                 and col_block 0 */
-    uint32_t reserved[2];
+    uint32_t bound_group;    /* matrix-core path: admission bounds before the
+                                search (BDG_BOUND_*): 0 = default (on, pivot
+                                groups of BDG_BOUND_GROUP_DEFAULT rows, or the
+                                autotuned setting with path AUTO and col_block
+                                0), BDG_BOUND_OFF, or rows per pivot group
+                                (BDG_BOUND_GROUP_MIN..BDG_BOUND_GROUP_MAX).
+                                The graph is the same either way */
+    uint32_t reserved;
 } bdg_knn_opts;
+
+/* Admission bounds (matrix-core path). Before the exhaustive search every row
+ * gets an upper bound on its K-th neighbour distance: the K-th smallest
+ * distance to the other members of its group, where pivots are every
+ * bound_group-th row of the partition and each row joins its nearest pivot's
+ * group. Any K other rows of the partition bound the final K-th distance from
+ * above, so admitting only candidates at most the bound while a row's list is
+ * not full leaves the graph unchanged; it spares the admissions of far
+ * candidates seen before the row's own cluster (the first reduce of Sec. 3.2
+ * searches a partition exhaustively, in input order). Costs about
+ * n * n / bound_group pair distances and (8 bits / 64 + 10) n bytes of
+ * workspace. */
+#define BDG_BOUND_OFF 1u
+#define BDG_BOUND_GROUP_DEFAULT 256u
+#define BDG_BOUND_GROUP_MIN 16u
+#define BDG_BOUND_GROUP_MAX (1u << 24)
 
 /* Tile schedules of the matrix-core build and of batched plans. They differ
  * in the LDS split between the rows' pending-key buffers and the stage ring
@@ -305,6 +328,9 @@ typedef struct bdg_batch_info {
     uint32_t shards, rows, work_items, workgroups;
     int32_t order;         /* BDG_ORDER_* */
     int32_t schedule;      /* BDG_SCHEDULE_* */
+    uint32_t bound_group;  /* rows per pivot group of the admission bounds, or
+                              BDG_BOUND_OFF */
+    uint32_t reserved;
     uint64_t pairs;        /* sum over shards of n_s (n_s - 1) */
     size_t device_bytes;   /* device memory held by the plan */
 } bdg_batch_info;
@@ -323,6 +349,11 @@ int bdg_batch_plan_info(const bdg_batch_plan *plan, bdg_batch_info *info);
 /* Change the tile schedule (BDG_SCHEDULE_*; drops a captured graph);
  * BDG_EUNSUPPORTED if the schedule is not built for the plan's code length. */
 int bdg_batch_plan_set_schedule(bdg_batch_plan *plan, int schedule);
+/* Change the admission bounds (bound_group as in bdg_knn_opts: 0 = default,
+ * BDG_BOUND_OFF, or rows per pivot group; uploads the pivot table, drops a
+ * captured graph, waits for queued work first). The graph is the same either
+ * way. A plan whose shards all have at most K + 1 rows has no bounds. */
+int bdg_batch_plan_set_bound(bdg_batch_plan *plan, uint32_t bound_group);
 /* Change the work order (re-uploads the work list; drops a captured graph).
  * Waits for all work queued on the device first, so a launch of the plan
  * still in flight on any stream finishes with the old list. A plan holds one

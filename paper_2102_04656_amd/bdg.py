@@ -52,7 +52,8 @@ class KnnOpts(ctypes.Structure):
         ("tile_events", ctypes.c_void_p),
         ("wait_limit", ctypes.c_uint32),
         ("tile_schedule", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 2),
+        ("bound_group", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
     ]
 
 
@@ -64,6 +65,8 @@ class BatchInfo(ctypes.Structure):
         ("workgroups", ctypes.c_uint32),
         ("order", ctypes.c_int32),
         ("schedule", ctypes.c_int32),
+        ("bound_group", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
         ("pairs", ctypes.c_uint64),
         ("device_bytes", ctypes.c_size_t),
     ]
@@ -71,6 +74,7 @@ class BatchInfo(ctypes.Structure):
 
 ORDER_LONGEST_FIRST, ORDER_SHARD = 0, 1
 SCHEDULE_DEFAULT, SCHEDULE_DEEP_RING = 0, 1
+BOUND_OFF, BOUND_GROUP_DEFAULT, BOUND_GROUP_MIN, BOUND_GROUP_MAX = 1, 256, 16, 1 << 24
 
 
 class MlpParams(ctypes.Structure):
@@ -130,6 +134,7 @@ _SIGS = {
     "bdg_batch_plan_info": [_p, _p],
     "bdg_batch_plan_set_order": [_p, ctypes.c_int],
     "bdg_batch_plan_set_schedule": [_p, ctypes.c_int],
+    "bdg_batch_plan_set_bound": [_p, ctypes.c_uint32],
     "bdg_build_knn_batched_plan": [_p, _p, _p, _p, _p],
     "bdg_build_knn_batched_graph": [_p, _p, _p, _p, _p],
     "bdg_build_knn_batched_ex": [_p, _p, _u32, _u32, _u32, _p, _p, _p, _p],
@@ -266,7 +271,7 @@ def bdg_version() -> int:
 
 def build_knn(codes, K: int, bits: int | None = None, path: int = PATH_AUTO,
               row_block: int = 0, col_block: int = 0, stream=None, out=None,
-              schedule: int = SCHEDULE_DEFAULT):
+              schedule: int = SCHEDULE_DEFAULT, bound_group: int = 0):
     """Exact Hamming kNN graph of ``codes`` (int64 ``[n][W]`` on the GPU).
 
     Returns ``(idx int32 [n][K], dist int16 [n][K])`` on the GPU (uint32 /
@@ -277,7 +282,8 @@ def build_knn(codes, K: int, bits: int | None = None, path: int = PATH_AUTO,
     if out is None:
         out = (torch.empty((n, K), dtype=torch.int32, device=codes.device),
                torch.empty((n, K), dtype=torch.int16, device=codes.device))
-    opts = make_opts(path=path, row_block=row_block, col_block=col_block, tile_schedule=schedule)
+    opts = make_opts(path=path, row_block=row_block, col_block=col_block, tile_schedule=schedule,
+                     bound_group=bound_group)
     _check(bdg_build_knn_ex(codes, n, bits, K, out[0], out[1], opts, stream))
     return out
 
@@ -372,12 +378,12 @@ class BatchPlan:
     (``bdg_batch_plan_*``). ``offsets`` is a host array of S + 1 row offsets."""
 
     def __init__(self, offsets, bits: int, K: int, order: int = ORDER_LONGEST_FIRST,
-                 schedule: int = SCHEDULE_DEFAULT):
+                 schedule: int = SCHEDULE_DEFAULT, bound_group: int = 0):
         off, ptr = _host_offsets(offsets)
         self.offsets, self.bits, self.K = off, bits, K
         self.S = off.size - 1
         h = ctypes.c_void_p()
-        o = make_opts(tile_variant=order, tile_schedule=schedule)
+        o = make_opts(tile_variant=order, tile_schedule=schedule, bound_group=bound_group)
         _check(lib().bdg_batch_plan_create(ptr, self.S, bits, K, ctypes.byref(o), ctypes.byref(h)))
         self.handle = h
 
@@ -391,6 +397,9 @@ class BatchPlan:
 
     def set_schedule(self, schedule: int):
         _check(lib().bdg_batch_plan_set_schedule(self.handle, schedule))
+
+    def set_bound(self, bound_group: int):
+        _check(lib().bdg_batch_plan_set_bound(self.handle, bound_group))
 
     def outputs(self, device="cuda"):
         import torch

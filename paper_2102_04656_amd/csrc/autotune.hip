@@ -40,6 +40,7 @@ struct Tuned {
   int path;
   uint32_t col_block;
   int schedule;
+  uint32_t bound_group;  // 0: the library default
 };
 
 std::mutex g_mu;
@@ -61,12 +62,14 @@ void load_cache_locked() {
   if (!f) return;
   char line[512];
   while (fgets(line, sizeof line, f)) {
-    unsigned bits = 0, K = 0, bucket = 0, cb = 0;
+    unsigned bits = 0, K = 0, bucket = 0, cb = 0, bg = 0;
     int p = 0, sc = 0;
+    const char* b = strstr(line, "\"bound_group\"");
+    if (b) sscanf(b, "\"bound_group\": %u", &bg);
     if (strstr(line, "\"kind\": \"build\"") &&
         sscanf(strstr(line, "\"bits\""), "\"bits\": %u, \"K\": %u, \"bucket\": %u, \"path\": %d, "
                "\"col_block\": %u, \"schedule\": %d", &bits, &K, &bucket, &p, &cb, &sc) == 6)
-      g_cache[std::make_tuple(bits, K, bucket)] = Tuned{p, cb, sc};
+      g_cache[std::make_tuple(bits, K, bucket)] = Tuned{p, cb, sc, bg};
   }
   fclose(f);
 }
@@ -114,7 +117,7 @@ int time_ms(F&& fn, hipStream_t stream, int reps, float* ms) {
 
 // The tuned schedule of a single build, if any (path AUTO, col_block 0).
 bool tuned_schedule(uint32_t n, uint32_t bits, uint32_t K, int* path, uint32_t* col_block,
-                    int* schedule) {
+                    int* schedule, uint32_t* bound_group) {
   std::lock_guard<std::mutex> lk(g_mu);
   load_cache_locked();
   auto it = g_cache.find(std::make_tuple(bits, K, size_bucket(n)));
@@ -122,6 +125,7 @@ bool tuned_schedule(uint32_t n, uint32_t bits, uint32_t K, int* path, uint32_t* 
   *path = it->second.path;
   *col_block = it->second.col_block;
   *schedule = it->second.schedule;
+  *bound_group = it->second.bound_group;
   return true;
 }
 
@@ -137,89 +141,132 @@ int bdg_autotune_build(const uint64_t* codes, uint32_t n, uint32_t bits, uint32_
     return bdg::api_error(BDG_EINVAL, "opts must be a full bdg_knn_opts");
   if (!codes || !out_idx || !out_dist) return bdg::api_error(BDG_EINVAL, "null device pointer");
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  // Coordinate search from the library's defaults: each knob in turn (column
+  // block, tile schedule, admission bounds) is swept with the others at their
+  // best so far; then the vector-ALU path. Candidates a build does not support
+  // are skipped.
   struct Cand {
     int path;
     uint32_t col_block;
     int schedule;
+    uint32_t bound_group;
     float ms;
   };
-  std::vector<Cand> cands;
-  for (int sc = 0; sc < bdg::kTileSchedules; ++sc)
-    for (uint32_t cb : {131072u, 262144u, 524288u}) cands.push_back({BDG_PATH_MFMA, cb, sc, 0.f});
-  cands.push_back({BDG_PATH_POPC, 131072u, 0, 0.f});
-  // the candidates this build supports, and one workspace large enough for all
-  size_t ws = 0;
   std::vector<Cand> ok;
-  for (const Cand& c : cands) {
+  void* buf = nullptr;
+  size_t buf_bytes = 0;
+  auto same = [&](const Cand& a, const Cand& b) {
+    return a.path == b.path && a.schedule == b.schedule && a.bound_group == b.bound_group &&
+           (a.col_block == b.col_block || (a.col_block >= n && b.col_block >= n));
+  };
+  // time one candidate (or reuse its time); returns its index in ok, or -1 if
+  // the build does not support it, or -2 - status on an error
+  auto run = [&](Cand c) -> long {
+    for (size_t i = 0; i < ok.size(); ++i)
+      if (same(ok[i], c)) return (long)i;
     bdg_knn_opts o = *opts;
     o.path = c.path;
     o.col_block = c.col_block;
     o.tile_schedule = (uint32_t)c.schedule;
+    o.bound_group = c.bound_group;
     o.workspace = nullptr;
     o.workspace_bytes = 0;
     o.n_tile_events = 0;
     o.tile_events = nullptr;
     size_t b = 0;
-    if (bdg_build_knn_workspace_size(n, bits, K, &o, &b) == BDG_OK) {
-      // a column block wider than the input is the same schedule as the input's width
-      bool dup = false;
-      for (const Cand& d : ok)
-        dup |= d.path == c.path && d.schedule == c.schedule && d.col_block >= n && c.col_block >= n;
-      if (!dup) ok.push_back(c);
-      if (b > ws) ws = b;
+    if (bdg_build_knn_workspace_size(n, bits, K, &o, &b) != BDG_OK) {
+      bdg::api_clear_error();
+      return -1;
     }
-  }
-  bdg::api_clear_error();
-  if (ok.empty()) return bdg::api_error(BDG_EUNSUPPORTED, "no schedule supports these arguments");
-  void* buf = nullptr;
-  if (ws) {
-    hipError_t e = hipMalloc(&buf, ws);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      return bdg::api_error(BDG_ENOMEM, "autotune workspace of %zu bytes failed", ws);
+    if (b > buf_bytes) {
+      if (buf) (void)hipFree(buf);
+      buf = nullptr;
+      buf_bytes = 0;
+      hipError_t e = hipMalloc(&buf, b);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return -2 - bdg::api_error(BDG_ENOMEM, "autotune workspace of %zu bytes failed", b);
+      }
+      buf_bytes = b;
     }
-  }
-  int st = BDG_OK;
-  size_t best = 0;
-  for (size_t i = 0; i < ok.size() && st == BDG_OK; ++i) {
-    bdg_knn_opts o = *opts;
-    o.path = ok[i].path;
-    o.col_block = ok[i].col_block;
-    o.tile_schedule = (uint32_t)ok[i].schedule;
     o.workspace = buf;
-    o.workspace_bytes = ws;
-    o.n_tile_events = 0;
-    o.tile_events = nullptr;
-    st = bdg::time_ms([&] { return bdg_build_knn_ex(codes, n, bits, K, out_idx, out_dist, &o,
-                                                    stream); },
-                      stream, 2, &ok[i].ms);
-    if (st == BDG_OK && ok[i].ms < ok[best].ms) best = i;
+    o.workspace_bytes = buf_bytes;
+    const int st = bdg::time_ms([&] { return bdg_build_knn_ex(codes, n, bits, K, out_idx, out_dist,
+                                                              &o, stream); },
+                                stream, 2, &c.ms);
+    if (st != BDG_OK) return -2 - st;
+    ok.push_back(c);
+    return (long)ok.size() - 1;
+  };
+  Cand best{BDG_PATH_MFMA, 262144u, 0, BDG_BOUND_GROUP_DEFAULT, 0.f};
+  long bi = -1;
+  int st = BDG_OK;
+  auto sweep = [&](std::vector<Cand> cs) {
+    for (const Cand& c : cs) {
+      if (st != BDG_OK) return;
+      const long r = run(c);
+      if (r <= -2) {
+        st = (int)(-2 - r);
+        return;
+      }
+      if (r >= 0 && (bi < 0 || ok[r].ms < ok[bi].ms)) bi = r;
+    }
+    if (bi >= 0) best = ok[bi];
+  };
+  {
+    std::vector<Cand> cs;
+    for (uint32_t cb : {262144u, 131072u, 524288u}) cs.push_back({BDG_PATH_MFMA, cb, 0, best.bound_group, 0.f});
+    sweep(cs);
   }
+  {
+    std::vector<Cand> cs;
+    for (int sc = 0; sc < bdg::kTileSchedules; ++sc) {
+      Cand c = best;
+      c.schedule = sc;
+      cs.push_back(c);
+    }
+    sweep(cs);
+  }
+  {
+    std::vector<Cand> cs;
+    for (uint32_t bg : {BDG_BOUND_GROUP_DEFAULT, BDG_BOUND_OFF, 64u, 1024u}) {
+      Cand c = best;
+      c.bound_group = bg;
+      cs.push_back(c);
+    }
+    sweep(cs);
+  }
+  sweep({{BDG_PATH_POPC, 131072u, 0, BDG_BOUND_GROUP_DEFAULT, 0.f}});
   if (buf) (void)hipFree(buf);
   if (st != BDG_OK) return st;
-  opts->path = ok[best].path;
-  opts->col_block = ok[best].col_block;
-  opts->tile_schedule = (uint32_t)ok[best].schedule;
+  bdg::api_clear_error();
+  if (bi < 0) return bdg::api_error(BDG_EUNSUPPORTED, "no schedule supports these arguments");
+  const Cand& w = ok[bi];
+  opts->path = w.path;
+  opts->col_block = w.col_block;
+  opts->tile_schedule = (uint32_t)w.schedule;
+  opts->bound_group = w.bound_group;
   {
     std::lock_guard<std::mutex> lk(bdg::g_mu);
     bdg::load_cache_locked();
     bdg::g_cache[std::make_tuple(bits, K, bdg::size_bucket(n))] =
-        bdg::Tuned{ok[best].path, ok[best].col_block, ok[best].schedule};
+        bdg::Tuned{w.path, w.col_block, w.schedule, w.bound_group};
   }
   char line[512];
   snprintf(line, sizeof line,
            "{\"kind\": \"build\", \"bits\": %u, \"K\": %u, \"bucket\": %u, \"path\": %d, "
-           "\"col_block\": %u, \"schedule\": %d, \"n\": %u, \"ms\": %.3f}",
-           bits, K, bdg::size_bucket(n), ok[best].path, ok[best].col_block, ok[best].schedule, n,
-           ok[best].ms);
+           "\"col_block\": %u, \"schedule\": %d, \"bound_group\": %u, \"n\": %u, \"ms\": %.3f}",
+           bits, K, bdg::size_bucket(n), w.path, w.col_block, w.schedule, w.bound_group, n, w.ms);
   bdg::append_cache_line(line);
   std::string rep = "{\"chosen\": ";
   rep += line;
-  rep += ", \"knobs\": [\"path\", \"col_block\", \"schedule\"], \"candidates\": [";
+  rep += ", \"knobs\": [\"path\", \"col_block\", \"schedule\", \"bound_group\"], \"candidates\": [";
   for (size_t i = 0; i < ok.size(); ++i) {
-    char c[160];
-    snprintf(c, sizeof c, "%s{\"path\": %d, \"col_block\": %u, \"schedule\": %d, \"ms\": %.3f}",
-             i ? ", " : "", ok[i].path, ok[i].col_block, ok[i].schedule, ok[i].ms);
+    char c[200];
+    snprintf(c, sizeof c,
+             "%s{\"path\": %d, \"col_block\": %u, \"schedule\": %d, \"bound_group\": %u, "
+             "\"ms\": %.3f}",
+             i ? ", " : "", ok[i].path, ok[i].col_block, ok[i].schedule, ok[i].bound_group, ok[i].ms);
     rep += c;
   }
   rep += "]}";
@@ -234,17 +281,26 @@ int bdg_autotune_batched(bdg_batch_plan* plan, const uint64_t* codes, uint32_t* 
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
   struct Cand {
     int order, schedule;
+    uint32_t bound_group;
     float ms;
   };
   std::vector<Cand> cands;
-  for (int sc = 0; sc < bdg::kTileSchedules; ++sc)
-    for (int order : {BDG_ORDER_LONGEST_FIRST, BDG_ORDER_SHARD}) cands.push_back({order, sc, 0.f});
+  for (uint32_t bg : {BDG_BOUND_GROUP_DEFAULT, BDG_BOUND_OFF})
+    for (int sc = 0; sc < bdg::kTileSchedules; ++sc)
+      for (int order : {BDG_ORDER_LONGEST_FIRST, BDG_ORDER_SHARD})
+        cands.push_back({order, sc, bg, 0.f});
   int st = BDG_OK;
   size_t best = 0;
   std::vector<Cand> ok;
   for (Cand c : cands) {
     if (bdg_batch_plan_set_schedule(plan, c.schedule) != BDG_OK) continue;  // not built here
-    st = bdg_batch_plan_set_order(plan, c.order);
+    st = bdg_batch_plan_set_bound(plan, c.bound_group);
+    if (st == BDG_OK) {
+      bdg_batch_info in;
+      bdg_batch_plan_info(plan, &in);
+      if (in.bound_group != c.bound_group) continue;  // a plan without bounds: one setting
+    }
+    if (st == BDG_OK) st = bdg_batch_plan_set_order(plan, c.order);
     if (st == BDG_OK)
       st = bdg::time_ms([&] { return bdg_build_knn_batched_plan(plan, codes, out_idx, out_dist,
                                                                  stream); },
@@ -256,6 +312,7 @@ int bdg_autotune_batched(bdg_batch_plan* plan, const uint64_t* codes, uint32_t* 
   bdg::api_clear_error();
   if (ok.empty()) return bdg::api_error(BDG_EUNSUPPORTED, "no schedule supports this plan");
   st = bdg_batch_plan_set_schedule(plan, ok[best].schedule);
+  if (st == BDG_OK) st = bdg_batch_plan_set_bound(plan, ok[best].bound_group);
   if (st == BDG_OK) st = bdg_batch_plan_set_order(plan, ok[best].order);
   if (st != BDG_OK) return st;
   bdg_batch_info info;
@@ -263,16 +320,18 @@ int bdg_autotune_batched(bdg_batch_plan* plan, const uint64_t* codes, uint32_t* 
   char line[256];
   snprintf(line, sizeof line,
            "{\"kind\": \"batched\", \"shards\": %u, \"rows\": %u, \"order\": %d, "
-           "\"schedule\": %d, \"ms\": %.3f}",
-           info.shards, info.rows, ok[best].order, ok[best].schedule, ok[best].ms);
+           "\"schedule\": %d, \"bound_group\": %u, \"ms\": %.3f}",
+           info.shards, info.rows, ok[best].order, ok[best].schedule, ok[best].bound_group,
+           ok[best].ms);
   bdg::append_cache_line(line);
   std::string rep = "{\"chosen\": ";
   rep += line;
-  rep += ", \"knobs\": [\"order\", \"schedule\"], \"candidates\": [";
+  rep += ", \"knobs\": [\"order\", \"schedule\", \"bound_group\"], \"candidates\": [";
   for (size_t i = 0; i < ok.size(); ++i) {
-    char c[128];
-    snprintf(c, sizeof c, "%s{\"order\": %d, \"schedule\": %d, \"ms\": %.3f}", i ? ", " : "",
-             ok[i].order, ok[i].schedule, ok[i].ms);
+    char c[160];
+    snprintf(c, sizeof c,
+             "%s{\"order\": %d, \"schedule\": %d, \"bound_group\": %u, \"ms\": %.3f}",
+             i ? ", " : "", ok[i].order, ok[i].schedule, ok[i].bound_group, ok[i].ms);
     rep += c;
   }
   rep += "]}";

@@ -37,11 +37,18 @@ struct bdg_batch_plan {
   int order = BDG_ORDER_LONGEST_FIRST;
   int schedule = 0;               // tile schedule (BDG_SCHEDULE_*)
   std::vector<uint64_t> offsets;  // host copy, S + 1 entries
-  void* dev = nullptr;            // items | counter | operand fragments
+  void* dev = nullptr;            // items | counter | operand fragments | bounds
   size_t dev_bytes = 0;
   bdg::BatchItem* items = nullptr;
   uint32_t* counter = nullptr;
   void* frags = nullptr;
+  // admission bounds: rows per pivot group (0: none), pivots, and the device
+  // segment tables (shard first rows, first pivots), bounds and scratch
+  uint32_t bgroup = 0, npiv = 0, base = 0, total = 0;
+  uint32_t* seg = nullptr;
+  uint32_t* pseg = nullptr;
+  uint16_t* bound = nullptr;
+  void* bscr = nullptr;
   // captured launch sequence and the arguments it was captured with
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -105,10 +112,58 @@ int upload_items(bdg_batch_plan* p) {
   return BDG_OK;
 }
 
+// Pivots of every shard for a group size (the first pivot of shard s at
+// pseg[s]); the scratch is sized for the smallest group size.
+std::vector<uint32_t> pivot_offsets(const std::vector<uint64_t>& off, uint32_t group) {
+  std::vector<uint32_t> ps(off.size(), 0);
+  for (size_t s = 0; s + 1 < off.size(); ++s)
+    ps[s + 1] = ps[s] + bdg::bound_pivots((uint32_t)(off[s + 1] - off[s]), group);
+  return ps;
+}
+
+// Set the admission-bound group size (BDG_BOUND_OFF: none) and upload its
+// pivot table. A set-up call: waits for queued work first.
+int set_bound_group(bdg_batch_plan* p, uint32_t group) {
+  if (group != BDG_BOUND_OFF && (group < BDG_BOUND_GROUP_MIN || group > BDG_BOUND_GROUP_MAX))
+    return bdg::api_error(BDG_EUNSUPPORTED, "bound_group %u outside [%u, %u] (or BDG_BOUND_OFF)",
+                          group, BDG_BOUND_GROUP_MIN, BDG_BOUND_GROUP_MAX);
+  const uint32_t g = (group == BDG_BOUND_OFF || !p->seg) ? 0u : group;
+  if (g == p->bgroup) return BDG_OK;
+  hipError_t e = hipDeviceSynchronize();
+  if (g) {
+    const std::vector<uint32_t> ps = pivot_offsets(p->offsets, g);
+    if (e == hipSuccess)
+      e = hipMemcpy(p->pseg, ps.data(), ps.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    p->npiv = ps.back();
+  }
+  if (e != hipSuccess) return bdg::api_device_error(e, "bound table upload");
+  p->bgroup = g;
+  drop_graph(p);
+  return BDG_OK;
+}
+
 int enqueue(const bdg_batch_plan* p, const uint64_t* codes, uint32_t* out_idx, uint16_t* out_dist,
             hipStream_t stream) {
   if (p->nitems == 0) return BDG_OK;
   hipError_t e = bdg::launch_prep(codes, p->n_total, p->words, p->frags, stream);
+  if (e == hipSuccess && p->bgroup) {
+    bdg::BoundArgs b;
+    b.codes = codes;
+    b.words = p->words;
+    b.bits = p->bits;
+    b.K = p->K;
+    b.group = p->bgroup;
+    b.cap = 1023;
+    b.nseg = p->S;
+    b.seg = p->seg;
+    b.pseg = p->pseg;
+    b.base = p->base;
+    b.total = p->total;
+    b.npiv = p->npiv;
+    b.scratch = p->bscr;
+    b.bound = p->bound;
+    e = bdg::launch_bounds_pass(b, stream);
+  }
   if (e == hipSuccess) {
     bdg::BatchArgs a;
     a.codes = codes;
@@ -124,6 +179,8 @@ int enqueue(const bdg_batch_plan* p, const uint64_t* codes, uint32_t* out_idx, u
     a.out_idx = out_idx;
     a.out_dist = out_dist;
     a.schedule = p->schedule;
+    a.bound = p->bgroup ? p->bound : nullptr;
+    a.bound_base = p->base;
     e = bdg::launch_mfma_batched(a, stream);
   }
   if (e != hipSuccess) return bdg::api_device_error(e, "batched launch");
@@ -189,6 +246,25 @@ int bdg_batch_plan_create(const uint64_t* offsets, uint32_t S, uint32_t bits, ui
   const size_t items_bytes = align256((size_t)std::max<uint32_t>(p->nitems, 1) *
                                       sizeof(bdg::BatchItem));
   p->dev_bytes = items_bytes + 256 + align256(bdg::prep_bytes(p->n_total, words));
+  // admission bounds: shards with more than K + 1 rows exist
+  uint32_t bgroup = (opts && opts->struct_size >= sizeof(bdg_knn_opts)) ? opts->bound_group : 0;
+  if (bgroup == 0) bgroup = BDG_BOUND_GROUP_DEFAULT;
+  if (bgroup != BDG_BOUND_OFF && (bgroup < BDG_BOUND_GROUP_MIN || bgroup > BDG_BOUND_GROUP_MAX)) {
+    delete p;
+    return bdg::api_error(BDG_EUNSUPPORTED, "bound_group %u outside [%u, %u] (or BDG_BOUND_OFF)",
+                          bgroup, BDG_BOUND_GROUP_MIN, BDG_BOUND_GROUP_MAX);
+  }
+  p->base = (uint32_t)offsets[0];
+  p->total = (uint32_t)(offsets[S] - offsets[0]);
+  size_t seg_off = 0, pseg_off = 0, bound_off = 0, bscr_off = 0;
+  if (largest > K + 1) {
+    const uint32_t npiv_max = pivot_offsets(p->offsets, BDG_BOUND_GROUP_MIN).back();
+    seg_off = p->dev_bytes;
+    pseg_off = seg_off + align256(((size_t)S + 1) * 4);
+    bound_off = pseg_off + align256(((size_t)S + 1) * 4);
+    bscr_off = bound_off + align256((size_t)p->total * 2);
+    p->dev_bytes = bscr_off + bdg::bound_scratch_bytes(p->total, words, npiv_max);
+  }
   const char* fail = getenv("BDG_TEST_FAIL_ALLOC");
   if (fail && fail[0] == '1') {
     delete p;
@@ -204,7 +280,23 @@ int bdg_batch_plan_create(const uint64_t* offsets, uint32_t S, uint32_t bits, ui
   p->items = static_cast<bdg::BatchItem*>(p->dev);
   p->counter = reinterpret_cast<uint32_t*>(static_cast<char*>(p->dev) + items_bytes);
   p->frags = static_cast<char*>(p->dev) + items_bytes + 256;
-  int st = upload_items(p);
+  int st = BDG_OK;
+  if (seg_off) {
+    char* d = static_cast<char*>(p->dev);
+    p->seg = reinterpret_cast<uint32_t*>(d + seg_off);
+    p->pseg = reinterpret_cast<uint32_t*>(d + pseg_off);
+    p->bound = reinterpret_cast<uint16_t*>(d + bound_off);
+    p->bscr = d + bscr_off;
+    std::vector<uint32_t> sg(p->offsets.begin(), p->offsets.end());
+    e = hipMemcpy(p->seg, sg.data(), sg.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) st = bdg::api_device_error(e, "bound table upload");
+    if (st == BDG_OK) st = set_bound_group(p, bgroup);
+    if (st != BDG_OK) {
+      bdg_batch_plan_destroy(p);
+      return st;
+    }
+  }
+  st = upload_items(p);
   if (st != BDG_OK) {
     bdg_batch_plan_destroy(p);
     return st;
@@ -228,6 +320,8 @@ int bdg_batch_plan_info(const bdg_batch_plan* plan, bdg_batch_info* info) {
   info->workgroups = plan->grid;
   info->order = plan->order;
   info->schedule = plan->schedule;
+  info->bound_group = plan->bgroup ? plan->bgroup : BDG_BOUND_OFF;
+  info->reserved = 0;
   uint64_t pairs = 0;
   for (uint32_t s = 0; s < plan->S; ++s) {
     const uint64_t ns = plan->offsets[s + 1] - plan->offsets[s];
@@ -261,6 +355,12 @@ int bdg_batch_plan_set_schedule(bdg_batch_plan* plan, int schedule) {
   plan->schedule = schedule;
   drop_graph(plan);  // the captured launch holds the old kernel
   return BDG_OK;
+}
+
+int bdg_batch_plan_set_bound(bdg_batch_plan* plan, uint32_t bound_group) {
+  if (!plan) return bdg::api_error(BDG_EINVAL, "plan is NULL");
+  if (bound_group == 0) bound_group = BDG_BOUND_GROUP_DEFAULT;
+  return set_bound_group(plan, bound_group);
 }
 
 int bdg_build_knn_batched_plan(const bdg_batch_plan* plan, const uint64_t* codes,

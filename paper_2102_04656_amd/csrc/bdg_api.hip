@@ -20,7 +20,7 @@
 
 namespace bdg {
 bool tuned_schedule(uint32_t n, uint32_t bits, uint32_t K, int* path, uint32_t* col_block,
-                    int* schedule);
+                    int* schedule, uint32_t* bound_group);
 }  // namespace bdg
 
 namespace {
@@ -62,10 +62,16 @@ struct Plan {
   int path;
   int schedule;     // matrix-core tile schedule
   bool running;     // lists carried across column blocks in the output rows
-  size_t ws_bytes;  // operand fragments + sweep control words (running), or
-                    // partial lists of one row block
-  size_t ws_idx_off, ws_dist_off, ws_ctl_off;
+  uint32_t bgroup;  // admission bounds: rows per pivot group (0: none)
+  uint32_t npiv;
+  size_t ws_bytes;  // operand fragments + sweep control words (+ admission
+                    // bounds and their scratch) (running), or partial lists
+                    // of one row block
+  size_t ws_idx_off, ws_dist_off, ws_ctl_off, ws_bound_off, ws_bscr_off;
 };
+
+// Members measured per row by the admission-bound pass, at most.
+constexpr uint32_t kBoundCap = 1023;
 
 int path_auto(uint32_t n, uint32_t words, uint32_t K) {
   if (bdg::run_supported(n, words, K)) return bdg::kPathMfma;
@@ -87,14 +93,21 @@ int make_plan(uint32_t n, uint32_t bits, uint32_t K, const bdg_knn_opts* opts, P
   int path = opts ? opts->path : BDG_PATH_AUTO;
   const bool full_opts = opts && opts->struct_size >= sizeof(bdg_knn_opts);
   int schedule = full_opts ? (int)opts->tile_schedule : 0;
+  uint32_t bgroup = full_opts ? opts->bound_group : 0;
   uint32_t tuned_cb = 0;
   if (path == BDG_PATH_AUTO && !(opts && opts->col_block)) {
     int tp = 0, ts = 0;
-    if (bdg::tuned_schedule(n, bits, K, &tp, &tuned_cb, &ts)) {
+    uint32_t tb = 0;
+    if (bdg::tuned_schedule(n, bits, K, &tp, &tuned_cb, &ts, &tb)) {
       path = tp;
       if (!(full_opts && opts->tile_schedule)) schedule = ts;
+      if (!(full_opts && opts->bound_group)) bgroup = tb;
     }
   }
+  if (bgroup == 0) bgroup = BDG_BOUND_GROUP_DEFAULT;
+  if (bgroup != BDG_BOUND_OFF && (bgroup < BDG_BOUND_GROUP_MIN || bgroup > BDG_BOUND_GROUP_MAX))
+    return set_error(BDG_EUNSUPPORTED, "bound_group %u outside [%u, %u] (or BDG_BOUND_OFF)",
+                     bgroup, BDG_BOUND_GROUP_MIN, BDG_BOUND_GROUP_MAX);
   if (path == BDG_PATH_AUTO) path = path_auto(n, p->words, K);
   if (path != BDG_PATH_POPC && path != BDG_PATH_MFMA)
     return set_error(BDG_EINVAL, "unknown path %d", path);
@@ -125,11 +138,20 @@ int make_plan(uint32_t n, uint32_t bits, uint32_t K, const bdg_knn_opts* opts, P
   if (p->ncb > 65535)
     return set_error(BDG_EUNSUPPORTED, "more than 65535 column blocks (col_block %u)", cb);
   p->running = path == BDG_PATH_MFMA;
-  p->ws_ctl_off = 0;
+  p->ws_ctl_off = p->ws_bound_off = p->ws_bscr_off = 0;
+  p->bgroup = p->npiv = 0;
   if (p->running) {
     p->ws_ctl_off = n ? align256(bdg::prep_bytes(n, p->words)) : 0;
     p->ws_bytes = n ? p->ws_ctl_off + align256(bdg::sweep_ctl_words(n, K) * 4) : 0;
     p->ws_idx_off = p->ws_dist_off = 0;
+    // bounds only help where a row has more than K candidates
+    if (bgroup != BDG_BOUND_OFF && n > K + 1) {
+      p->bgroup = bgroup;
+      p->npiv = bdg::bound_pivots(n, bgroup);
+      p->ws_bound_off = p->ws_bytes;
+      p->ws_bscr_off = p->ws_bound_off + align256((size_t)n * 2);
+      p->ws_bytes = p->ws_bscr_off + bdg::bound_scratch_bytes(n, p->words, p->npiv);
+    }
   } else if (p->ncb > 1) {
     const size_t entries = (size_t)p->ncb * rb * K;
     p->ws_idx_off = 0;
@@ -228,6 +250,25 @@ int bdg_build_knn_ex(const uint64_t* codes, uint32_t n, uint32_t bits, uint32_t 
     // against every column block in one persistent launch, each (row tile,
     // column block) item merging its columns into the rows' running lists.
     hipError_t e = bdg::launch_prep(codes, n, p.words, ws, stream);
+    uint16_t* bound = nullptr;
+    if (e == hipSuccess && p.bgroup) {
+      bound = reinterpret_cast<uint16_t*>(static_cast<char*>(ws) + p.ws_bound_off);
+      bdg::BoundArgs b;
+      b.codes = codes;
+      b.words = p.words;
+      b.bits = bits;
+      b.K = K;
+      b.group = p.bgroup;
+      b.cap = kBoundCap;
+      b.nseg = 1;
+      b.seg = b.pseg = nullptr;  // one segment: rows [0, n), pivots [0, npiv)
+      b.base = 0;
+      b.total = n;
+      b.npiv = p.npiv;
+      b.scratch = static_cast<char*>(ws) + p.ws_bscr_off;
+      b.bound = bound;
+      e = bdg::launch_bounds_pass(b, stream);
+    }
     int dev = 0, cus = 0;
     if (e == hipSuccess) e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -251,6 +292,7 @@ int bdg_build_knn_ex(const uint64_t* codes, uint32_t n, uint32_t bits, uint32_t 
       a.out_dist = out_dist + (size_t)r0 * K;
       a.spin_limit = (opts && opts->struct_size >= sizeof(bdg_knn_opts)) ? opts->wait_limit : 0;
       a.schedule = p.schedule;
+      a.bound = bound;
       const bool timed = opts && opts->tile_events && opts->n_tile_events >= 2;
       if (timed) e = hipEventRecord(reinterpret_cast<hipEvent_t>(opts->tile_events[0]), stream);
       if (e == hipSuccess) e = bdg::launch_mfma_sweep(a, stream);

@@ -121,6 +121,11 @@ struct BatchArgs {
   uint32_t* out_idx;
   uint16_t* out_dist;
   int schedule = 0;        // tile schedule (schedule_supported)
+  // Admission bounds (launch_bounds_pass) of the rows [bound_base, ...), or
+  // nullptr: while a row's list is not full, only candidates at a distance of
+  // at most its bound are admitted.
+  const uint16_t* bound = nullptr;
+  uint32_t bound_base = 0;
 };
 hipError_t launch_mfma_batched(const BatchArgs& a, hipStream_t stream);
 
@@ -142,9 +147,37 @@ struct SweepArgs {
   uint16_t* out_dist;
   uint32_t spin_limit = 0;  // polls of one dependency wait before it gives up (0: default)
   int schedule = 0;         // tile schedule (schedule_supported)
+  const uint16_t* bound = nullptr;  // admission bounds of rows [0, ...), or nullptr
 };
 constexpr uint32_t kSweepStallWord = 1;  // ctl[1] != 0: a dependency wait ran out
 size_t sweep_ctl_words(uint32_t nrows, uint32_t K);
 hipError_t launch_mfma_sweep(const SweepArgs& a, hipStream_t stream);
+
+// Admission bounds (bound.hip). Rows [seg[0], seg[nseg]) of `codes` form
+// nseg segments (partitions; a row's neighbours are the other rows of its
+// segment). Segment s has pivots = its rows seg[s] + j * group, j <
+// ceil(size / group), numbered from pseg[s]; every row joins the group of its
+// nearest pivot, and its bound is the K-th smallest distance to up to `cap`
+// other members of that group, or 0xFFFF where the group has fewer than K
+// others. Any K other rows of the segment bound the K-th distance of the
+// graph row from above, so a tile that admits only candidates at most the
+// bound while a list is not full still computes the exact graph.
+struct BoundArgs {
+  const uint64_t* codes;
+  uint32_t words, bits, K;
+  uint32_t group;        // rows per pivot
+  uint32_t cap;          // other group members measured per row, at most
+  uint32_t nseg;
+  const uint32_t* seg;   // device [nseg + 1] first rows (ascending); nullptr
+                         // with nseg = 1: rows [base, base + total)
+  const uint32_t* pseg;  // device [nseg + 1] first pivots; nullptr: [0, npiv)
+  uint32_t base, total;  // seg[0] and seg[nseg] - seg[0] (host copies)
+  uint32_t npiv;         // pseg[nseg] (host copy)
+  void* scratch;         // bound_scratch_bytes(total, words, npiv), 256-aligned
+  uint16_t* bound;       // [total] output: row base + i at bound[i]
+};
+size_t bound_scratch_bytes(uint32_t total, uint32_t words, uint32_t npiv);
+uint32_t bound_pivots(uint32_t rows, uint32_t group);  // ceil(rows / group)
+hipError_t launch_bounds_pass(const BoundArgs& a, hipStream_t stream);
 
 }  // namespace bdg

@@ -156,12 +156,16 @@ __device__ __forceinline__ int flush_sub(uint32_t* list_q, const uint32_t* buf_q
 // of the rows live in out_idx/out_dist (row row0 + r at r * K); unless
 // `fresh` they hold the merge of earlier column blocks. Keys and output
 // indices are columns minus colbase (0: global indices; a shard's first row:
-// shard-local indices).
+// shard-local indices). `bound` (row row0 + r at r), if not null, holds an
+// upper bound on each row's final K-th distance (0xFFFF: none): while a list
+// is not full only candidates at most the bound are admitted, which keeps the
+// result exact and spares the admissions of far candidates seen early.
 struct TileJob {
   uint32_t row0, nrows, cb, ce, colbase;
   int fresh;
   uint32_t* out_idx;
   uint16_t* out_dist;
+  const uint16_t* bound;
 };
 
 constexpr int kMaxWaves = 8;  // compute waves of a work-group, at most
@@ -329,6 +333,7 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
   v4i bq[QG][W];
   int biasQ[QG];
   int popcq[QG];
+  int capB[QG];  // bias while the list is not full: bound + 1 - popc(q)
   uint32_t qrow[QG], csub[QG];
 #pragma unroll
   for (int gq = 0; gq < QG; ++gq) {
@@ -342,11 +347,18 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
       pc += __popcll(codes[(size_t)row * W + s]);
     }
     int bias = -(int)bits - 1;  // absent row: acc <= popc(q) - bits - 1 < 0, never passes
+    int cap = (int)bits + 1;
     if (valid) {
+      if (job.bound) {
+        const uint32_t b = job.bound[ql];
+        if (b < bits) cap = (int)b + 1;
+      }
       const uint32_t kth = list_w[(16 * gq + i16) * K + K - 1];
-      bias = (kth == kKeyNone ? (int)bits + 1 : (int)(kth >> IB)) - pc;
+      // a full list holds only keys admitted under the bound: kth <= bound
+      bias = (kth == kKeyNone ? cap : (int)(kth >> IB)) - pc;
     }
     biasQ[gq] = bias;
+    capB[gq] = cap - pc;
     popcq[gq] = pc;
     qrow[gq] = row0 + ql;
     csub[gq] = 0;
@@ -372,7 +384,7 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
           __builtin_amdgcn_readlane(csub[gq], 16 + i), __builtin_amdgcn_readlane(csub[gq], 32 + i),
           __builtin_amdgcn_readlane(csub[gq], 48 + i), K, lane, IB, bits);
       if (i16 == i) {
-        biasQ[gq] = thr - popcq[gq];
+        biasQ[gq] = min(thr - popcq[gq], capB[gq]);
         csub[gq] = 0;
       }
       wave_sync();
@@ -714,7 +726,8 @@ template <int W, int NR, int QG, int GPS, int NST, int KB>
 __global__ __launch_bounds__(threads_of(W, NR), 1) void knn_mfma_batched_kernel(
     const v4i* __restrict__ frags, const uint64_t* __restrict__ codes, uint32_t K, uint32_t bits,
     uint32_t IB, const BatchItem* __restrict__ items, uint32_t nitems, uint32_t* counter,
-    uint32_t* __restrict__ out_idx, uint16_t* __restrict__ out_dist) {
+    uint32_t* __restrict__ out_idx, uint16_t* __restrict__ out_dist,
+    const uint16_t* __restrict__ bound, uint32_t bound_base) {
   __shared__ TileRing<GPS * W * 64, NST> ring;
   __shared__ uint32_t cur;
   extern __shared__ uint32_t state[];
@@ -734,6 +747,7 @@ __global__ __launch_bounds__(threads_of(W, NR), 1) void knn_mfma_batched_kernel(
     job.fresh = 1;
     job.out_idx = out_idx + (size_t)b.row0 * K;
     job.out_dist = out_dist + (size_t)b.row0 * K;
+    job.bound = bound ? bound + (b.row0 - bound_base) : nullptr;
     tile_body<W, NR, QG, GPS, NST, use_producer(W, NR), waves_of_nr(NR), KB>(
         frags, codes, K, bits, IB, job, 0, ring, state);
   }
@@ -760,7 +774,7 @@ __global__ __launch_bounds__(threads_of(W, NR), 1) void knn_mfma_sweep_kernel(
     const v4i* __restrict__ frags, const uint64_t* __restrict__ codes, uint32_t K, uint32_t bits,
     uint32_t IB, uint32_t row0, uint32_t nrows, uint32_t ncols, uint32_t col_block,
     uint32_t ntiles, uint32_t nitems, uint32_t* ctl, uint32_t* __restrict__ out_idx,
-    uint16_t* __restrict__ out_dist, uint32_t spin_limit) {
+    uint16_t* __restrict__ out_dist, uint32_t spin_limit, const uint16_t* __restrict__ bound) {
   __shared__ TileRing<GPS * W * 64, NST> ring;
   __shared__ uint32_t cur;
   extern __shared__ uint32_t state[];
@@ -798,6 +812,7 @@ __global__ __launch_bounds__(threads_of(W, NR), 1) void knn_mfma_sweep_kernel(
     job.fresh = c == 0;
     job.out_idx = out_idx + (size_t)t * RT * K;
     job.out_dist = out_dist + (size_t)t * RT * K;
+    job.bound = bound ? bound + job.row0 : nullptr;
     tile_body<W, NR, QG, GPS, NST, use_producer(W, NR), waves_of_nr(NR), KB>(
         frags, codes, K, bits, IB, job, 0, ring, state);
     // the tile's lists are in the output rows: publish them
@@ -863,6 +878,7 @@ inline hipError_t launch_run_w(const RunArgs& a, hipStream_t stream) {
   job.fresh = a.fresh;
   job.out_idx = a.out_idx;
   job.out_dist = a.out_dist;
+  job.bound = nullptr;
   hipLaunchKernelGGL(kern, grid, dim3(threads_of(W, NR)), lds, stream,
                      reinterpret_cast<const v4i*>(a.frags), a.codes, a.K, a.bits, a.idx_bits, job);
   return hipGetLastError();
@@ -882,7 +898,7 @@ inline hipError_t launch_batched_w(const BatchArgs& a, hipStream_t stream) {
   hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, stream, a.counter);
   hipLaunchKernelGGL(kern, dim3(a.grid), dim3(threads_of(W, NR)), lds, stream,
                      reinterpret_cast<const v4i*>(a.frags), a.codes, a.K, a.bits, a.idx_bits,
-                     a.items, a.nitems, a.counter, a.out_idx, a.out_dist);
+                     a.items, a.nitems, a.counter, a.out_idx, a.out_dist, a.bound, a.bound_base);
   return hipGetLastError();
 }
 
@@ -909,7 +925,7 @@ inline hipError_t launch_sweep_w(const SweepArgs& a, hipStream_t stream) {
   hipLaunchKernelGGL(kern, dim3(grid), dim3(threads_of(W, NR)), lds, stream,
                      reinterpret_cast<const v4i*>(a.frags), a.codes, a.K, a.bits, a.idx_bits,
                      a.row0, a.nrows, a.ncols, a.col_block, ntiles, nitems, a.ctl, a.out_idx,
-                     a.out_dist, a.spin_limit ? a.spin_limit : kSweepSpinLimit);
+                     a.out_dist, a.spin_limit ? a.spin_limit : kSweepSpinLimit, a.bound);
   return hipGetLastError();
 }
 

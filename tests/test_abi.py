@@ -85,18 +85,35 @@ def test_workspace_size():
     ws = bdg.bdg_build_knn_workspace_size(1000, 256, 8, o)
     ent = 4 * 300 * 8
     assert ws == ((ent * 4 + 255) // 256) * 256 + ((ent * 2 + 255) // 256) * 256
-    # matrix-core path: the +-1 operand fragments of all codes (bits bytes per row,
-    # rows rounded up to 16 plus 256 rows of slack), whatever the blocking, then
-    # the sweep's control words (2 + one per tile of 256 rows for K <= 64),
-    # each part aligned to 256 bytes
+    # matrix-core path: the {0, 1} operand fragments of all codes (bits bytes per
+    # row, rows rounded up to 16 plus 256 rows of slack), whatever the blocking,
+    # then the sweep's control words (2 + one per tile of 256 rows for K <= 64),
+    # each part aligned to 256 bytes; without admission bounds
+    a256 = lambda x: (x + 255) // 256 * 256
+    off = bdg.BOUND_OFF
     for kw in (dict(), dict(col_block=250, row_block=300)):
-        o = bdg.make_opts(path=bdg.PATH_MFMA, **kw)
+        o = bdg.make_opts(path=bdg.PATH_MFMA, bound_group=off, **kw)
         ws = bdg.bdg_build_knn_workspace_size(1000, 256, 8, o)
-        assert ws == (((1000 + 15) // 16 * 16 + 256) * 256 + 255) // 256 * 256 + 256
-    o = bdg.make_opts(path=bdg.PATH_MFMA)
+        assert ws == a256(((1000 + 15) // 16 * 16 + 256) * 256) + 256
+    o = bdg.make_opts(path=bdg.PATH_MFMA, bound_group=off)
     n = 300_000  # 1,172 tiles of 256 rows: 1,174 control words
-    ws = bdg.bdg_build_knn_workspace_size(n, 128, 64, o)
-    assert ws == (((n + 15) // 16 * 16 + 256) * 128 + 255) // 256 * 256 + (1174 * 4 + 255) // 256 * 256
+    ws0 = bdg.bdg_build_knn_workspace_size(n, 128, 64, o)
+    assert ws0 == a256(((n + 15) // 16 * 16 + 256) * 128) + a256(1174 * 4)
+    # with them (the default, pivot groups of 256 rows): the bounds (2 bytes a
+    # row), then nearest pivots and group members (4 bytes a row each), group
+    # offsets and cursors (4 bytes a pivot each, one more offset) and the codes
+    # in group order
+    for group in (0, 256, 100, 16):
+        g = group or 256
+        npiv = (n + g - 1) // g
+        o = bdg.make_opts(path=bdg.PATH_MFMA, bound_group=group)
+        ws = bdg.bdg_build_knn_workspace_size(n, 128, 64, o)
+        assert ws == ws0 + a256(2 * n) + 2 * a256(4 * n) + a256(4 * (npiv + 1)) + \
+            a256(4 * npiv) + a256(16 * n), group
+    # n <= K + 1: no row has more candidates than it keeps, no bounds
+    o = bdg.make_opts(path=bdg.PATH_MFMA)
+    assert bdg.bdg_build_knn_workspace_size(65, 128, 64, o) == \
+        a256(((65 + 15) // 16 * 16 + 256) * 128) + a256(3 * 4)
 
 
 def test_batched_plan_rejects_bad_arguments():
@@ -167,3 +184,12 @@ def test_probe_peak_validates_before_touching_the_gpu():
     assert L.bdg_probe_peak(5, ctypes.byref(rate), None) == bdg.BDG_EINVAL
     assert "unknown unit" in bdg.last_error()
     assert L.bdg_probe_peak(bdg.PEAK_VALU_INT32, None, None) == bdg.BDG_EINVAL
+
+
+def test_bound_group_validation():
+    L = bdg.lib()
+    for g in (2, 15, (1 << 24) + 1):
+        o = bdg.make_opts(path=bdg.PATH_MFMA, bound_group=g)
+        assert call_ex(bits=256, opts=o) == bdg.BDG_EUNSUPPORTED, g
+        assert "bound_group" in bdg.last_error()
+    assert L.bdg_batch_plan_set_bound(None, 256) == bdg.BDG_EINVAL

@@ -125,12 +125,47 @@ def test_orders_graph_replay_and_autotune_agree():
     stream.synchronize()
     got = to_np(out)
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+    # admission bounds off, and other pivot-group sizes: the same graph
+    for group in (bdg.BOUND_OFF, 16, 1024, bdg.BOUND_GROUP_DEFAULT):
+        plan.set_bound(group)
+        assert plan.info().bound_group == group
+        got = to_np(plan.build(d))
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), group
+        out[0].zero_()
+        torch.cuda.synchronize()
+        plan.build(d, out=out, stream=stream, graph=True)
+        stream.synchronize()
+        got = to_np(out)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), group
     report = plan.autotune(d)
     assert '"kind": "batched"' in report and '"schedule"' in report
     import json
-    assert len(json.loads(report)["candidates"]) == 4
+    rep = json.loads(report)
+    assert rep["knobs"] == ["order", "schedule", "bound_group"]
+    assert len(rep["candidates"]) == 8
     got = to_np(plan.build(d))
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+    # every candidate the tuner timed builds the same graph
+    for c in rep["candidates"]:
+        plan.set_order(c["order"])
+        plan.set_schedule(c["schedule"])
+        plan.set_bound(c["bound_group"])
+        got = to_np(plan.build(d))
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), c
+    plan.close()
+
+
+def test_plans_without_bounds():
+    # every shard has at most K + 1 rows: no row has more candidates than it
+    # keeps, so the plan carries no bounds whatever it is asked for
+    codes, offsets = shard_codes([5, 17, 0, 33, 1], 128, seed=13)
+    plan = bdg.BatchPlan(offsets, 128, 32, bound_group=64)
+    assert plan.info().bound_group == bdg.BOUND_OFF
+    plan.set_bound(256)
+    assert plan.info().bound_group == bdg.BOUND_OFF
+    gi, gd = to_np(plan.build(dev(codes)))
+    for s in range(5):
+        check_shard(gi, gd, codes, offsets, s, 32)
     plan.close()
 
 
@@ -230,15 +265,16 @@ def test_autotune_build_keeps_the_graph():
     assert '"chosen"' in report
     import json
     rep = json.loads(report)
-    assert rep["knobs"] == ["path", "col_block", "schedule"]
+    assert rep["knobs"] == ["path", "col_block", "schedule", "bound_group"]
     cands = rep["candidates"]
-    assert {c["schedule"] for c in cands} == {0, 1} and len(cands) >= 3
+    assert {c["schedule"] for c in cands} == {0, 1} and len(cands) >= 5
+    assert {bdg.BOUND_OFF, bdg.BOUND_GROUP_DEFAULT} <= {c["bound_group"] for c in cands}
     rows = np.arange(0, 20_000, 97)
     # every candidate schedule the tuner timed builds the same graph
     for c in cands:
         print(f"[autotune] candidate {c}", flush=True)
         ci, cd = to_np(bdg.build_knn(d, 32, path=c["path"], col_block=c["col_block"],
-                                     schedule=c["schedule"]))
+                                     schedule=c["schedule"], bound_group=c["bound_group"]))
         assert np.array_equal(ci[rows], want[0]) and np.array_equal(cd[rows], want[1]), c
     idx, dist = bdg.build_knn(d, 32, path=opts.path, col_block=opts.col_block)
     gi, gd = to_np((idx, dist))

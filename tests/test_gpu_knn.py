@@ -124,6 +124,47 @@ def test_paths_agree_and_are_deterministic():
         assert_same(gpu_knn(codes, 64, POPC, col_block=cb), a, f"popc col_block={cb}")
 
 
+# ---------------------------------------------------- admission bounds
+
+BOUND_CASES = [
+    # n, bits, K, n_centres, p
+    (3000, 256, 16, 30, 0.2),
+    (5000, 512, 100, 25, 0.25),   # lists of 65..128: four waves of 48 rows
+    (2000, 128, 200, 20, 0.15),   # lists of 129..256
+    (2500, 192, 33, 1000, 0.2),   # clusters smaller than K: many rows without a bound
+    (1200, 1024, 64, 12, 0.25),
+    (700, 64, 8, 3, 0.3),
+]
+
+
+@pytest.mark.parametrize("n,bits,K,nc,p", BOUND_CASES)
+def test_admission_bounds_keep_the_graph(n, bits, K, nc, p):
+    codes = datagen.clustered_codes(n, bits, nc, p, seed=n + bits + K)
+    want = oracle.knn_rows(codes, K)
+    for group in (bdg.BOUND_OFF, 16, 64, bdg.BOUND_GROUP_DEFAULT, 4096, bdg.BOUND_GROUP_MAX):
+        print(f"[bounds] n={n} bits={bits} K={K} group={group}", flush=True)
+        assert_same(gpu_knn(codes, K, MFMA, bound_group=group), want, f"group={group}")
+        if group == 64:
+            # several column blocks: the bound also holds for lists carried across them
+            assert_same(gpu_knn(codes, K, MFMA, bound_group=group, col_block=n // 3 + 1), want,
+                        f"group={group} col_block={n // 3 + 1}")
+
+
+def test_admission_bounds_on_ties():
+    # identical codes: every bound is 0, and the list is the smallest indices
+    codes = np.tile(datagen.uniform_codes(1, 256, seed=5), (700, 1))
+    for group in (16, bdg.BOUND_GROUP_DEFAULT):
+        assert_same(gpu_knn(codes, 50, MFMA, bound_group=group), oracle.knn_rows(codes, 50),
+                    f"identical group={group}")
+    # 40 distinct codes repeated: ties at the bound decided by index
+    g = np.random.default_rng(17)
+    base = datagen.clustered_codes(40, 128, 4, 0.2, seed=9)
+    codes = base[g.integers(0, 40, 3000)]
+    for K in (30, 64, 150):
+        assert_same(gpu_knn(codes, K, MFMA, bound_group=32), oracle.knn_rows(codes, K),
+                    f"repeated K={K}")
+
+
 # ------------------------------------------------------ named workloads
 
 def test_clustered_20k_128b_k32_full():
