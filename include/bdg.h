@@ -108,14 +108,14 @@ typedef struct bdg_knn_opts {
 
 /* Admission bounds (matrix-core path). Before the exhaustive search every row
  * gets an upper bound on its K-th neighbour distance: the K-th smallest
- * distance to the other members of its group, where pivots are every
- * bound_group-th row of the partition and each row joins its nearest pivot's
- * group. Any K other rows of the partition bound the final K-th distance from
+ * distance to the other members of its group and of the group of its
+ * second-nearest pivot, where pivots are every bound_group-th row of the
+ * partition and each row joins its nearest pivot's group. Any K other rows of the partition bound the final K-th distance from
  * above, so admitting only candidates at most the bound while a row's list is
  * not full leaves the graph unchanged; it spares the admissions of far
  * candidates seen before the row's own cluster (the first reduce of Sec. 3.2
  * searches a partition exhaustively, in input order). Costs about
- * n * n / bound_group pair distances and (8 bits / 64 + 10) n bytes of
+ * n * n / bound_group pair distances and (bits / 8 + 14) n bytes of
  * workspace. */
 #define BDG_BOUND_OFF 1u
 #define BDG_BOUND_GROUP_DEFAULT 256u

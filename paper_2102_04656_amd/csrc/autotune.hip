@@ -229,7 +229,7 @@ int bdg_autotune_build(const uint64_t* codes, uint32_t n, uint32_t bits, uint32_
   }
   {
     std::vector<Cand> cs;
-    for (uint32_t bg : {BDG_BOUND_GROUP_DEFAULT, BDG_BOUND_OFF, 64u, 1024u}) {
+    for (uint32_t bg : {BDG_BOUND_GROUP_DEFAULT, BDG_BOUND_OFF, 128u, 512u, 64u}) {
       Cand c = best;
       c.bound_group = bg;
       cs.push_back(c);
@@ -279,36 +279,67 @@ int bdg_autotune_batched(bdg_batch_plan* plan, const uint64_t* codes, uint32_t* 
   bdg::api_clear_error();
   if (!plan) return bdg::api_error(BDG_EINVAL, "plan is NULL");
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  // Coordinate search from the plan's defaults: the work order, then the tile
+  // schedule, then the admission bounds, each swept with the others at their
+  // best so far. Settings a plan does not support are skipped.
   struct Cand {
     int order, schedule;
     uint32_t bound_group;
     float ms;
   };
-  std::vector<Cand> cands;
-  for (uint32_t bg : {BDG_BOUND_GROUP_DEFAULT, BDG_BOUND_OFF})
-    for (int sc = 0; sc < bdg::kTileSchedules; ++sc)
-      for (int order : {BDG_ORDER_LONGEST_FIRST, BDG_ORDER_SHARD})
-        cands.push_back({order, sc, bg, 0.f});
-  int st = BDG_OK;
-  size_t best = 0;
   std::vector<Cand> ok;
-  for (Cand c : cands) {
-    if (bdg_batch_plan_set_schedule(plan, c.schedule) != BDG_OK) continue;  // not built here
-    st = bdg_batch_plan_set_bound(plan, c.bound_group);
-    if (st == BDG_OK) {
+  size_t best = 0;
+  int st = BDG_OK;
+  Cand cur{BDG_ORDER_LONGEST_FIRST, 0, BDG_BOUND_GROUP_DEFAULT, 0.f};
+  auto sweep = [&](std::vector<Cand> cs) {
+    for (Cand c : cs) {
+      if (st != BDG_OK) return;
+      bool seen = false;
+      for (const Cand& o : ok)
+        seen |= o.order == c.order && o.schedule == c.schedule && o.bound_group == c.bound_group;
+      if (seen) continue;
+      if (bdg_batch_plan_set_schedule(plan, c.schedule) != BDG_OK) continue;  // not built here
+      st = bdg_batch_plan_set_bound(plan, c.bound_group);
+      if (st != BDG_OK) return;
       bdg_batch_info in;
       bdg_batch_plan_info(plan, &in);
       if (in.bound_group != c.bound_group) continue;  // a plan without bounds: one setting
+      st = bdg_batch_plan_set_order(plan, c.order);
+      if (st == BDG_OK)
+        st = bdg::time_ms([&] { return bdg_build_knn_batched_plan(plan, codes, out_idx, out_dist,
+                                                                   stream); },
+                          stream, 1, &c.ms);
+      if (st != BDG_OK) return;
+      ok.push_back(c);
+      if (c.ms < ok[best].ms) best = ok.size() - 1;
     }
-    if (st == BDG_OK) st = bdg_batch_plan_set_order(plan, c.order);
-    if (st == BDG_OK)
-      st = bdg::time_ms([&] { return bdg_build_knn_batched_plan(plan, codes, out_idx, out_dist,
-                                                                 stream); },
-                        stream, 1, &c.ms);
-    if (st != BDG_OK) return st;
-    ok.push_back(c);
-    if (c.ms < ok[best].ms) best = ok.size() - 1;
+    if (!ok.empty()) cur = ok[best];
+  };
+  {
+    bdg_batch_info in;
+    bdg_batch_plan_info(plan, &in);
+    if (in.bound_group == BDG_BOUND_OFF) {
+      // no bounds unless the plan can take them
+      if (bdg_batch_plan_set_bound(plan, BDG_BOUND_GROUP_DEFAULT) == BDG_OK) {
+        bdg_batch_plan_info(plan, &in);
+        cur.bound_group = in.bound_group;
+      }
+    }
   }
+  sweep({{BDG_ORDER_LONGEST_FIRST, cur.schedule, cur.bound_group, 0.f},
+         {BDG_ORDER_SHARD, cur.schedule, cur.bound_group, 0.f}});
+  {
+    std::vector<Cand> cs;
+    for (int sc = 0; sc < bdg::kTileSchedules; ++sc) cs.push_back({cur.order, sc, cur.bound_group, 0.f});
+    sweep(cs);
+  }
+  {
+    std::vector<Cand> cs;
+    for (uint32_t bg : {BDG_BOUND_GROUP_DEFAULT, BDG_BOUND_OFF, 128u, 512u, 64u})
+      cs.push_back({cur.order, cur.schedule, bg, 0.f});
+    sweep(cs);
+  }
+  if (st != BDG_OK) return st;
   bdg::api_clear_error();
   if (ok.empty()) return bdg::api_error(BDG_EUNSUPPORTED, "no schedule supports this plan");
   st = bdg_batch_plan_set_schedule(plan, ok[best].schedule);

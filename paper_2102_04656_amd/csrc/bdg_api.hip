@@ -67,7 +67,7 @@ struct Plan {
   size_t ws_bytes;  // operand fragments + sweep control words (+ admission
                     // bounds and their scratch) (running), or partial lists
                     // of one row block
-  size_t ws_idx_off, ws_dist_off, ws_ctl_off, ws_bound_off, ws_bscr_off;
+  size_t ws_idx_off, ws_dist_off, ws_ctl_off, ws_bound_off, ws_bscr_off, ws_brect_off;
 };
 
 // Members measured per row by the admission-bound pass, at most.
@@ -138,7 +138,7 @@ int make_plan(uint32_t n, uint32_t bits, uint32_t K, const bdg_knn_opts* opts, P
   if (p->ncb > 65535)
     return set_error(BDG_EUNSUPPORTED, "more than 65535 column blocks (col_block %u)", cb);
   p->running = path == BDG_PATH_MFMA;
-  p->ws_ctl_off = p->ws_bound_off = p->ws_bscr_off = 0;
+  p->ws_ctl_off = p->ws_bound_off = p->ws_bscr_off = p->ws_brect_off = 0;
   p->bgroup = p->npiv = 0;
   if (p->running) {
     p->ws_ctl_off = n ? align256(bdg::prep_bytes(n, p->words)) : 0;
@@ -151,6 +151,12 @@ int make_plan(uint32_t n, uint32_t bits, uint32_t K, const bdg_knn_opts* opts, P
       p->ws_bound_off = p->ws_bytes;
       p->ws_bscr_off = p->ws_bound_off + align256((size_t)n * 2);
       p->ws_bytes = p->ws_bscr_off + bdg::bound_scratch_bytes(n, p->words, p->npiv);
+      // nearest pivots on the matrix cores where the tile takes the shape
+      const size_t rb = bdg::bound_rect_bytes(n, p->words, p->npiv);
+      if (rb) {
+        p->ws_brect_off = p->ws_bytes;
+        p->ws_bytes += rb;
+      }
     }
   } else if (p->ncb > 1) {
     const size_t entries = (size_t)p->ncb * rb * K;
@@ -267,6 +273,7 @@ int bdg_build_knn_ex(const uint64_t* codes, uint32_t n, uint32_t bits, uint32_t 
       b.npiv = p.npiv;
       b.scratch = static_cast<char*>(ws) + p.ws_bscr_off;
       b.bound = bound;
+      b.rect_scratch = p.ws_brect_off ? static_cast<char*>(ws) + p.ws_brect_off : nullptr;
       e = bdg::launch_bounds_pass(b, stream);
     }
     int dev = 0, cus = 0;

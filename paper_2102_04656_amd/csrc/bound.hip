@@ -13,8 +13,11 @@
 // every `group` rows of the partition (input order, so a strided sample), each
 // row joining the group of its nearest pivot (ties to the lower pivot), and
 // the bound is the K-th smallest distance to up to `cap` other members of its
-// group (the binary k-means of Sec. 3.2 groups similar codes the same way;
-// here the grouping only bounds an exact search). Where a group has fewer than
+// own group and up to `cap` members of the group of its second-nearest pivot
+// (a cluster larger than the group size holds several pivots, and two groups
+// cover more of it; the binary k-means of Sec. 3.2 groups similar codes the
+// same way and also lets a record join more than one partition; here the
+// grouping only bounds an exact search). Where the two groups have fewer than
 // K other members the row gets no bound (0xFFFF).
 //
 // Exactness: every candidate of the row's true top K lies at a distance of at
@@ -27,7 +30,7 @@
 // Steps (one segment per partition): nearest pivot of every row (one thread
 // per row, pivot codes read wave-uniformly when the wave's rows share a
 // segment), group sizes by atomics, one work-group's scan to group offsets,
-// a scatter of rows and codes into group order, and one wave per row (in
+// a scatter of rows and codes into group order, and 16 lanes per row (in
 // group order, so the group's codes stay in cache) measuring the group's
 // members into a histogram over distances 0..bits in LDS, whose prefix sums
 // give the K-th smallest.
@@ -40,7 +43,10 @@ namespace bdg {
 namespace {
 
 constexpr uint32_t kNoBound = 0xFFFFu;
-constexpr int kBoundWaves = 4;  // rows per work-group of the bound kernel
+constexpr uint32_t kKeyShift = 21;  // pivot field of a (distance, pivot) key
+constexpr uint32_t kKeyPivots = 1u << kKeyShift;
+constexpr int kBoundWaves = 4;  // waves per work-group of the bound kernel
+constexpr int kBoundSlots = 4;  // rows per wave of the bound kernel
 
 struct BK {
   const uint64_t* codes;
@@ -48,6 +54,7 @@ struct BK {
   const uint32_t* seg;   // nullptr: one segment [base, base + total)
   const uint32_t* pseg;  // nullptr: its pivots [0, npiv)
   uint32_t* nearest;  // [total] group of row base + i
+  uint32_t* second;   // [total] group of its second-nearest pivot (= nearest if none)
   uint32_t* offs;     // [npiv + 1] group sizes, then offsets
   uint32_t* cursor;   // [npiv]
   uint32_t* members;  // [total] rows (relative) in group order
@@ -98,37 +105,88 @@ __global__ __launch_bounds__(256) void nearest_pivot_kernel(BK a) {
   uint64_t q[W];
 #pragma unroll
   for (int w = 0; w < W; ++w) q[w] = a.codes[(size_t)r * W + w];
-  uint32_t best = 0xFFFFFFFFu, bj = 0, p0;
+  // nearest (b1, j1) and second-nearest (b2, j2) pivot, ties to the lower one
+  uint32_t b1 = 0xFFFFFFFFu, j1 = 0, b2 = 0xFFFFFFFFu, j2 = 0xFFFFFFFFu, p0;
+#define BDG_OFFER(dv, jv)                              \
+  do {                                                 \
+    const uint32_t d_ = (dv), jj_ = (jv);              \
+    const bool lt1_ = d_ < b1, lt2_ = d_ < b2;         \
+    b2 = lt1_ ? b1 : (lt2_ ? d_ : b2);                 \
+    j2 = lt1_ ? j1 : (lt2_ ? jj_ : j2);                \
+    b1 = lt1_ ? d_ : b1;                               \
+    j1 = lt1_ ? jj_ : j1;                              \
+  } while (0)
   const uint32_t s0 = __builtin_amdgcn_readfirstlane(s);
   if (__ballot(s != s0) == 0) {
     // every lane in one segment: the pivot codes are wave-uniform loads
     const uint32_t lo = __builtin_amdgcn_readfirstlane(a.seg ? a.seg[s0] : a.base);
     p0 = __builtin_amdgcn_readfirstlane(a.pseg ? a.pseg[s0] : 0u);
     const uint32_t np = __builtin_amdgcn_readfirstlane(a.pseg ? a.pseg[s0 + 1] : a.npiv) - p0;
-    for (uint32_t j = 0; j < np; ++j) {
-      const uint32_t d = ham_to<W>(q, a.codes + (size_t)(lo + j * a.group) * W);
-      if (d < best) {
-        best = d;
-        bj = j;
+    const uint64_t* pc = a.codes + (size_t)lo * W;
+    const size_t stride = (size_t)a.group * W;
+    uint32_t j = 0;
+    if (np <= kKeyPivots) {
+      // (distance, pivot) as one key, distance << 21 | pivot (distances are at
+      // most 1024): the two smallest keys by min / max; four pivots per step,
+      // their loads issued together
+      uint32_t k1 = 0xFFFFFFFFu, k2 = 0xFFFFFFFFu;
+#define BDG_PUT(dv, jv)                                   \
+  do {                                                    \
+    const uint32_t k_ = ((dv) << kKeyShift) | (jv);       \
+    k2 = min(k2, max(k1, k_));                            \
+    k1 = min(k1, k_);                                     \
+  } while (0)
+      for (; j + 4 <= np; j += 4) {
+        const uint64_t* c = pc + (size_t)j * stride;
+        const uint32_t d0 = ham_to<W>(q, c), d1 = ham_to<W>(q, c + stride);
+        const uint32_t d2 = ham_to<W>(q, c + 2 * stride), d3 = ham_to<W>(q, c + 3 * stride);
+        BDG_PUT(d0, j);
+        BDG_PUT(d1, j + 1);
+        BDG_PUT(d2, j + 2);
+        BDG_PUT(d3, j + 3);
       }
+      for (; j < np; ++j) BDG_PUT(ham_to<W>(q, pc + (size_t)j * stride), j);
+#undef BDG_PUT
+      j1 = k1 & (kKeyPivots - 1);
+      j2 = k2 == 0xFFFFFFFFu ? 0xFFFFFFFFu : (k2 & (kKeyPivots - 1));
+    } else {
+      for (; j < np; ++j) BDG_OFFER(ham_to<W>(q, pc + (size_t)j * stride), j);
     }
   } else {
     const uint32_t lo = a.seg ? a.seg[s] : a.base;
     p0 = a.pseg ? a.pseg[s] : 0u;
     const uint32_t np = (a.pseg ? a.pseg[s + 1] : a.npiv) - p0;
-    for (uint32_t j = 0; j < np; ++j) {
-      const uint32_t d = ham_to<W>(q, a.codes + (size_t)(lo + j * a.group) * W);
-      if (d < best) {
-        best = d;
-        bj = j;
-      }
-    }
+    for (uint32_t j = 0; j < np; ++j) BDG_OFFER(ham_to<W>(q, a.codes + (size_t)(lo + j * a.group) * W), j);
   }
+#undef BDG_OFFER
   if (live) {
-    const uint32_t g = p0 + bj;
+    const uint32_t g = p0 + j1;
     a.nearest[i] = g;
+    a.second[i] = j2 == 0xFFFFFFFFu ? g : p0 + j2;
     atomicAdd(&a.offs[g + 1], 1u);
   }
+}
+
+// Codes of the pivots of one segment, contiguous (for the matrix-core tile).
+__global__ __launch_bounds__(256) void gather_pivots_kernel(const uint64_t* __restrict__ codes,
+                                                            uint32_t base, uint32_t group,
+                                                            uint32_t npiv, uint32_t words,
+                                                            uint64_t* __restrict__ out) {
+  const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (size_t)npiv * words) return;
+  const size_t j = t / words, w = t - j * words;
+  out[t] = codes[((size_t)base + j * group) * words + w];
+}
+
+// Nearest and second-nearest pivot from the tile's two-element lists
+// ((distance, pivot) order; a missing second entry when there is one pivot).
+__global__ __launch_bounds__(256) void top2_kernel(BK a, const uint32_t* __restrict__ top) {
+  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.total) return;
+  const uint32_t g = top[2 * (size_t)i], g2 = top[2 * (size_t)i + 1];
+  a.nearest[i] = g;
+  a.second[i] = g2 == 0xFFFFFFFFu ? g : g2;
+  atomicAdd(&a.offs[g + 1], 1u);
 }
 
 // offs[1..npiv] (group sizes) -> inclusive prefix sums in place (offs[0] = 0),
@@ -170,84 +228,144 @@ __global__ __launch_bounds__(256) void scatter_group_kernel(BK a) {
   for (int w = 0; w < W; ++w) a.gcodes[(size_t)pos * W + w] = a.codes[(size_t)(a.base + i) * W + w];
 }
 
-// One wave per position of the group order: the row at that position against
-// up to cap + 1 members of its group (itself skipped), distances counted in a
-// histogram in LDS; the bound is the smallest distance with at least K members
-// at or below it.
+// Four rows per wave (16 lanes each, kBoundSlots slots), at consecutive
+// positions of the group order: the row against up to cap + 1 members of its
+// group (itself skipped) and up to cap members of its second group, distances
+// counted in the slot's histogram in LDS; the bound is the smallest distance
+// with at least K members at or below it. Several rows per wave keep several
+// chains of dependent loads (position -> row -> groups -> members) in flight.
 template <int W>
 __global__ __launch_bounds__(64 * kBoundWaves) void group_bound_kernel(BK a) {
-  extern __shared__ uint32_t hist_all[];
+  extern __shared__ uint32_t smem[];
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave = threadIdx.x >> 6;
-  const uint32_t pos = blockIdx.x * kBoundWaves + wave;
-  if (pos >= a.total) return;  // whole wave
+  const uint32_t slot = lane >> 4, sub = lane & 15u;
   const uint32_t nb = a.bits + 1;
-  uint32_t* hist = hist_all + wave * nb;
-  for (uint32_t x = lane; x < nb; x += 64) hist[x] = 0;
-  const uint32_t i = a.members[pos];
-  const uint32_t g = a.nearest[i];
-  const uint32_t gb = a.offs[g], ge = a.offs[g + 1];
-  const uint32_t m = (ge - gb) < a.cap + 1 ? (ge - gb) : a.cap + 1;
+  uint32_t* hist = smem + (wave * kBoundSlots + slot) * nb;
+  const uint32_t pos = (blockIdx.x * kBoundWaves + wave) * kBoundSlots + slot;
+  const bool live = pos < a.total;
+  for (uint32_t x = sub; x < nb; x += 16) hist[x] = 0;
+  uint32_t i = 0, m = 0, m2 = 0, gb = 0, gb2 = 0;
+  if (live) {
+    i = a.members[pos];
+    const uint32_t g = a.nearest[i], g2 = a.second[i];
+    gb = a.offs[g];
+    const uint32_t s1 = a.offs[g + 1] - gb;
+    m = s1 < a.cap + 1 ? s1 : a.cap + 1;
+    if (g2 != g) {
+      gb2 = a.offs[g2];
+      const uint32_t s2 = a.offs[g2 + 1] - gb2;
+      m2 = s2 < a.cap ? s2 : a.cap;
+    }
+  }
   uint64_t q[W];
 #pragma unroll
-  for (int w = 0; w < W; ++w) q[w] = a.gcodes[(size_t)pos * W + w];
-  wave_fence_sync();  // the cleared histogram before any count
-  for (uint32_t t = lane; t < m; t += 64) {
-    const uint32_t p = gb + t;
-    if (p != pos) atomicAdd(&hist[ham_to<W>(q, a.gcodes + (size_t)p * W)], 1u);
+  for (int w = 0; w < W; ++w) q[w] = live ? a.gcodes[(size_t)pos * W + w] : 0ull;
+  wave_fence_sync();  // the cleared histograms before any count
+  const uint32_t self = pos - gb;  // the row's place in its group (it is a member)
+  for (uint32_t t = sub; t < m + m2; t += 16) {
+    const uint32_t p = t < m ? gb + t : gb2 + (t - m);
+    if (t != self) atomicAdd(&hist[ham_to<W>(q, a.gcodes + (size_t)p * W)], 1u);
   }
   wave_fence_sync();
-  const uint32_t others = m - ((pos - gb) < m ? 1u : 0u);
-  uint32_t bnd = kNoBound;
-  if (others >= a.K) {
-    const uint32_t per = (nb + 63) / 64;
-    const uint32_t x0 = lane * per;
-    uint32_t sum = 0;
-    for (uint32_t k = 0; k < per; ++k)
-      if (x0 + k < nb) sum += hist[x0 + k];
-    uint32_t inc = sum;
+  // the row is a member of its own group only
+  const uint32_t others = m + m2 - (self < m ? 1u : 0u);
+  const bool want = live && others >= a.K;
+  // prefix sums over the slot's 16 lanes of their bins' counts
+  const uint32_t per = (nb + 15) / 16;
+  const uint32_t x0 = sub * per;
+  uint32_t sum = 0;
+  for (uint32_t k = 0; k < per; ++k)
+    if (x0 + k < nb) sum += hist[x0 + k];
+  uint32_t inc = sum;
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t v = __shfl_up(inc, off);
-      if (lane >= (uint32_t)off) inc += v;
-    }
-    const uint64_t hit = __ballot(inc >= a.K);  // nonzero: the last lane holds all `others`
-    const uint32_t L = (uint32_t)__builtin_ctzll(hit);
-    if (lane == L) {
-      uint32_t run = inc - sum;
-      for (uint32_t k = 0; k < per && x0 + k < nb; ++k) {
-        run += hist[x0 + k];
-        if (run >= a.K) {
-          bnd = x0 + k;
-          break;
-        }
+  for (int off = 1; off < 16; off <<= 1) {
+    const uint32_t v = __shfl_up(inc, off, 16);
+    if (sub >= (uint32_t)off) inc += v;
+  }
+  // the slot's first lane whose prefix reaches K (the last lane holds all `others`)
+  const uint64_t hit = __ballot(want && inc >= a.K);
+  const uint32_t mine = (uint32_t)(hit >> (16 * slot)) & 0xFFFFu;
+  if (want && mine && sub == (uint32_t)__builtin_ctz(mine)) {
+    uint32_t run = inc - sum, bnd = kNoBound;
+    for (uint32_t k = 0; k < per && x0 + k < nb; ++k) {
+      run += hist[x0 + k];
+      if (run >= a.K) {
+        bnd = x0 + k;
+        break;
       }
     }
-    bnd = __shfl(bnd, (int)L);
+    a.bound[i] = (uint16_t)bnd;
+  } else if (live && !want && sub == 0) {
+    a.bound[i] = (uint16_t)kNoBound;
   }
-  if (lane == 0) a.bound[i] = (uint16_t)bnd;
 }
 
 template <int W>
-hipError_t launch_words(const BK& k, hipStream_t stream) {
+hipError_t launch_words(const BK& k, const BoundArgs& a, hipStream_t stream) {
   const dim3 rows((k.total + 255) / 256);
-  hipLaunchKernelGGL(nearest_pivot_kernel<W>, rows, dim3(256), 0, stream, k);
+  if (a.rect_scratch && !a.seg) {
+    // every row against every pivot on the matrix cores: a rectangular tile
+    // with two-element lists (rows = the codes, columns = the pivots)
+    char* p = static_cast<char*>(a.rect_scratch);
+    uint64_t* pcodes = reinterpret_cast<uint64_t*>(p);
+    p += align256((size_t)k.npiv * W * 8);
+    void* pfrags = p;
+    p += align256(prep_bytes(k.npiv, W));
+    uint32_t* top = reinterpret_cast<uint32_t*>(p);
+    p += align256((size_t)k.total * 8);
+    uint16_t* tdist = reinterpret_cast<uint16_t*>(p);
+    hipLaunchKernelGGL(gather_pivots_kernel, dim3((unsigned)(((size_t)k.npiv * W + 255) / 256)),
+                       dim3(256), 0, stream, k.codes, k.base, k.group, k.npiv, (uint32_t)W, pcodes);
+    hipError_t e = launch_prep(pcodes, k.npiv, W, pfrags, stream);
+    if (e != hipSuccess) return e;
+    RunArgs r;
+    r.codes = k.codes;
+    r.frags = pfrags;
+    r.words = W;
+    r.bits = k.bits;
+    r.K = 2;
+    r.idx_bits = run_idx_bits(k.bits);
+    r.row0 = k.base;
+    r.nrows = k.total;
+    r.cb = 0;
+    r.ce = k.npiv;
+    r.fresh = 1;
+    r.out_idx = top;
+    r.out_dist = tdist;
+    r.rect = 1;
+    e = launch_mfma_run(r, stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(top2_kernel, rows, dim3(256), 0, stream, k, top);
+  } else {
+    hipLaunchKernelGGL(nearest_pivot_kernel<W>, rows, dim3(256), 0, stream, k);
+  }
   hipLaunchKernelGGL(group_scan_kernel, dim3(1), dim3(1024), 0, stream, k.offs, k.cursor, k.npiv);
   hipLaunchKernelGGL(scatter_group_kernel<W>, rows, dim3(256), 0, stream, k);
-  const size_t lds = (size_t)kBoundWaves * (k.bits + 1) * 4;
-  hipLaunchKernelGGL(group_bound_kernel<W>, dim3((k.total + kBoundWaves - 1) / kBoundWaves),
+  const size_t lds = (size_t)kBoundWaves * kBoundSlots * (k.bits + 1) * 4;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(group_bound_kernel<W>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const uint32_t per_wg = kBoundWaves * kBoundSlots;
+  hipLaunchKernelGGL(group_bound_kernel<W>, dim3((k.total + per_wg - 1) / per_wg),
                      dim3(64 * kBoundWaves), lds, stream, k);
   return hipGetLastError();
 }
 
 }  // namespace
 
+size_t bound_rect_bytes(uint32_t total, uint32_t words, uint32_t npiv) {
+  if (!run_supported(npiv, words, 2)) return 0;
+  return align256((size_t)npiv * words * 8) + align256(prep_bytes(npiv, words)) +
+         align256((size_t)total * 8) + align256((size_t)total * 4);
+}
+
 uint32_t bound_pivots(uint32_t rows, uint32_t group) {
   return (uint32_t)(((uint64_t)rows + group - 1) / group);
 }
 
 size_t bound_scratch_bytes(uint32_t total, uint32_t words, uint32_t npiv) {
-  return align256((size_t)total * 4) * 2 + align256(((size_t)npiv + 1) * 4) +
+  return align256((size_t)total * 4) * 3 + align256(((size_t)npiv + 1) * 4) +
          align256((size_t)npiv * 4) + align256((size_t)total * words * 8);
 }
 
@@ -272,6 +390,8 @@ hipError_t launch_bounds_pass(const BoundArgs& a, hipStream_t stream) {
   p += align256((size_t)a.total * 4);
   k.members = reinterpret_cast<uint32_t*>(p);
   p += align256((size_t)a.total * 4);
+  k.second = reinterpret_cast<uint32_t*>(p);
+  p += align256((size_t)a.total * 4);
   k.offs = reinterpret_cast<uint32_t*>(p);
   p += align256(((size_t)a.npiv + 1) * 4);
   k.cursor = reinterpret_cast<uint32_t*>(p);
@@ -281,22 +401,22 @@ hipError_t launch_bounds_pass(const BoundArgs& a, hipStream_t stream) {
   hipLaunchKernelGGL(clear_words_kernel, dim3((a.npiv + 1 + 255) / 256), dim3(256), 0, stream,
                      k.offs, a.npiv + 1);
   switch (a.words) {
-    case 1: return launch_words<1>(k, stream);
-    case 2: return launch_words<2>(k, stream);
-    case 3: return launch_words<3>(k, stream);
-    case 4: return launch_words<4>(k, stream);
-    case 5: return launch_words<5>(k, stream);
-    case 6: return launch_words<6>(k, stream);
-    case 7: return launch_words<7>(k, stream);
-    case 8: return launch_words<8>(k, stream);
-    case 9: return launch_words<9>(k, stream);
-    case 10: return launch_words<10>(k, stream);
-    case 11: return launch_words<11>(k, stream);
-    case 12: return launch_words<12>(k, stream);
-    case 13: return launch_words<13>(k, stream);
-    case 14: return launch_words<14>(k, stream);
-    case 15: return launch_words<15>(k, stream);
-    case 16: return launch_words<16>(k, stream);
+    case 1: return launch_words<1>(k, a, stream);
+    case 2: return launch_words<2>(k, a, stream);
+    case 3: return launch_words<3>(k, a, stream);
+    case 4: return launch_words<4>(k, a, stream);
+    case 5: return launch_words<5>(k, a, stream);
+    case 6: return launch_words<6>(k, a, stream);
+    case 7: return launch_words<7>(k, a, stream);
+    case 8: return launch_words<8>(k, a, stream);
+    case 9: return launch_words<9>(k, a, stream);
+    case 10: return launch_words<10>(k, a, stream);
+    case 11: return launch_words<11>(k, a, stream);
+    case 12: return launch_words<12>(k, a, stream);
+    case 13: return launch_words<13>(k, a, stream);
+    case 14: return launch_words<14>(k, a, stream);
+    case 15: return launch_words<15>(k, a, stream);
+    case 16: return launch_words<16>(k, a, stream);
     default: return hipErrorInvalidValue;
   }
 }

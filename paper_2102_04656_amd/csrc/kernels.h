@@ -158,8 +158,8 @@ hipError_t launch_mfma_sweep(const SweepArgs& a, hipStream_t stream);
 // segment). Segment s has pivots = its rows seg[s] + j * group, j <
 // ceil(size / group), numbered from pseg[s]; every row joins the group of its
 // nearest pivot, and its bound is the K-th smallest distance to up to `cap`
-// other members of that group, or 0xFFFF where the group has fewer than K
-// others. Any K other rows of the segment bound the K-th distance of the
+// other members of that group and up to `cap` members of the group of its
+// second-nearest pivot, or 0xFFFF where those are fewer than K. Any K other rows of the segment bound the K-th distance of the
 // graph row from above, so a tile that admits only candidates at most the
 // bound while a list is not full still computes the exact graph.
 struct BoundArgs {
@@ -175,8 +175,12 @@ struct BoundArgs {
   uint32_t npiv;         // pseg[nseg] (host copy)
   void* scratch;         // bound_scratch_bytes(total, words, npiv), 256-aligned
   uint16_t* bound;       // [total] output: row base + i at bound[i]
+  // one segment only: bound_rect_bytes(total, words, npiv) bytes (256-aligned)
+  // let the nearest pivots come from the matrix-core tile; nullptr: vector ALUs
+  void* rect_scratch = nullptr;
 };
 size_t bound_scratch_bytes(uint32_t total, uint32_t words, uint32_t npiv);
+size_t bound_rect_bytes(uint32_t total, uint32_t words, uint32_t npiv);  // 0: not supported
 uint32_t bound_pivots(uint32_t rows, uint32_t group);  // ceil(rows / group)
 hipError_t launch_bounds_pass(const BoundArgs& a, hipStream_t stream);
 

@@ -142,7 +142,10 @@ def test_orders_graph_replay_and_autotune_agree():
     import json
     rep = json.loads(report)
     assert rep["knobs"] == ["order", "schedule", "bound_group"]
-    assert len(rep["candidates"]) == 8
+    cands = rep["candidates"]
+    assert len(cands) == 7  # 2 orders, then the other schedule, then 4 more bound settings
+    assert {c["order"] for c in cands} == {0, 1} and {c["schedule"] for c in cands} == {0, 1}
+    assert {256, bdg.BOUND_OFF, 128, 512, 64} == {c["bound_group"] for c in cands}
     got = to_np(plan.build(d))
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
     # every candidate the tuner timed builds the same graph
