@@ -460,10 +460,12 @@ def bench_batched(args, w):
     plan = bdg.BatchPlan(offsets, bits, K, bound_group=args.bound_group)
     out = plan.outputs()
     stream = torch.cuda.Stream()
-    with torch.cuda.stream(stream):
-        report = plan.autotune(d, out=out, stream=stream)
-    stream.synchronize()
-    log(f"[bench] autotune: {report}")
+    report = None
+    if args.tune_batched:
+        with torch.cuda.stream(stream):
+            report = plan.autotune(d, out=out, stream=stream)
+        stream.synchronize()
+        log(f"[bench] autotune: {report}")
     ev = HipEvents(2 * args.steps)
     rt = ev.rt
     rt.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
@@ -502,6 +504,8 @@ def bench_batched(args, w):
                      "sustained_probe": peaks["mfma_int8"]},
         "measured_peaks_tops": peaks,
     }
+    if report:
+        result["autotune"] = json.loads(report)
     rec = recorded_traffic("knn_mfma_batched_kernel", args.workload)
     if rec is not None:
         result["roofline"]["traffic"] = rec["bytes_per_launch"]
@@ -673,6 +677,9 @@ def main():
     ap.add_argument("--bound-group", type=int, default=0,
                     help="admission bounds of the matrix-core build: rows per pivot group "
                          "(0: the library default, 1: off)")
+    ap.add_argument("--tune-batched", action=argparse.BooleanOptionalAction, default=True,
+                    help="batched workloads: tune the plan (work order, tile schedule, bound "
+                         "group) before the timed replays")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the build schedule (bdg_autotune_build) before the timed builds, "
                          "outside the timed region, and time the winner")
