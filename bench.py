@@ -484,8 +484,18 @@ def bench_batched(args, w):
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
     launch_ms = float(np.mean([ev.elapsed_ms(2 * s, 2 * s + 1) for s in range(args.steps)]))
     ev.close()
+    # the persistent kernel alone (events around it, eager enqueues of the same
+    # plan), apart from the operand prep and the admission bounds of a replay
+    kev = HipEvents(2 * args.steps)
+    for s in range(args.steps):
+        plan.set_timing(kev.handles[2 * s], kev.handles[2 * s + 1])
+        plan.build(d, out=out, stream=stream)
+    stream.synchronize()
+    plan.set_timing(None, None)
+    kernel_ms = float(np.mean([kev.elapsed_ms(2 * s, 2 * s + 1) for s in range(args.steps)]))
+    kev.close()
     info = plan.info()
-    achieved = pairs * 2 * bits / (launch_ms * 1e-3) / 1e12
+    achieved = pairs * 2 * bits / (kernel_ms * 1e-3) / 1e12
     result = {
         "metric": METRIC, "value": pairs / (ms * 1e-3), "unit": "pair-dist/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
@@ -495,11 +505,14 @@ def bench_batched(args, w):
                    "work_items": info.work_items, "workgroups": info.workgroups,
                    "order": "longest-first" if info.order == 0 else "shard",
                    "schedule": info.schedule, "bound_group": info.bound_group,
-                   "launch": "hip-graph (operand prep, admission bounds, persistent kernel; "
-                             "kernel_avg_ms times the whole replay)"},
+                   "launch": "hip-graph (operand prep, admission bounds, persistent kernel); "
+                             "kernel_avg_ms times the persistent kernel alone in eager builds, "
+                             "replay_avg_ms the whole replay"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_INT8_TOPS,
                      "unit": "TOP/s", "frac": achieved / PEAK_INT8_TOPS, "traffic": None,
-                     "kernel": "knn_mfma_batched_kernel", "kernel_avg_ms": launch_ms,
+                     "kernel": "knn_mfma_batched_kernel", "kernel_avg_ms": kernel_ms,
+                     "replay_avg_ms": launch_ms,
+                     "frac_replay": pairs * 2 * bits / (launch_ms * 1e-3) / 1e12 / PEAK_INT8_TOPS,
                      "ops_per_pair": 2 * bits, "pairs_per_launch": pairs,
                      "sustained_probe": peaks["mfma_int8"]},
         "measured_peaks_tops": peaks,

@@ -354,6 +354,12 @@ int bdg_batch_plan_set_schedule(bdg_batch_plan *plan, int schedule);
  * captured graph, waits for queued work first). The graph is the same either
  * way. A plan whose shards all have at most K + 1 rows has no bounds. */
 int bdg_batch_plan_set_bound(bdg_batch_plan *plan, uint32_t bound_group);
+/* Diagnostics: caller-created hipEvent_t handles recorded on the stream just
+ * before and just after the persistent kernel of every later
+ * bdg_build_knn_batched_plan call (not of graph replays), so that the kernel
+ * can be timed apart from the operand prep and the admission bounds. Both
+ * NULL stops it; one NULL is BDG_EINVAL. The plan does not own the events. */
+int bdg_batch_plan_set_timing(bdg_batch_plan *plan, void *start_event, void *stop_event);
 /* Change the work order (re-uploads the work list; drops a captured graph).
  * Waits for all work queued on the device first, so a launch of the plan
  * still in flight on any stream finishes with the old list. A plan holds one

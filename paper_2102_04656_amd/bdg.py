@@ -135,6 +135,7 @@ _SIGS = {
     "bdg_batch_plan_set_order": [_p, ctypes.c_int],
     "bdg_batch_plan_set_schedule": [_p, ctypes.c_int],
     "bdg_batch_plan_set_bound": [_p, ctypes.c_uint32],
+    "bdg_batch_plan_set_timing": [_p, _p, _p],
     "bdg_build_knn_batched_plan": [_p, _p, _p, _p, _p],
     "bdg_build_knn_batched_graph": [_p, _p, _p, _p, _p],
     "bdg_build_knn_batched_ex": [_p, _p, _u32, _u32, _u32, _p, _p, _p, _p],
@@ -400,6 +401,11 @@ class BatchPlan:
 
     def set_bound(self, bound_group: int):
         _check(lib().bdg_batch_plan_set_bound(self.handle, bound_group))
+
+    def set_timing(self, start_event, stop_event):
+        """hipEvent_t handles (ints) recorded around the persistent kernel of
+        eager builds; (None, None) stops."""
+        _check(lib().bdg_batch_plan_set_timing(self.handle, start_event, stop_event))
 
     def outputs(self, device="cuda"):
         import torch

@@ -49,6 +49,8 @@ struct bdg_batch_plan {
   uint32_t* pseg = nullptr;
   uint16_t* bound = nullptr;
   void* bscr = nullptr;
+  // optional events around the persistent kernel of eager enqueues
+  hipEvent_t ev_start = nullptr, ev_stop = nullptr;
   // captured launch sequence and the arguments it was captured with
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -143,7 +145,7 @@ int set_bound_group(bdg_batch_plan* p, uint32_t group) {
 }
 
 int enqueue(const bdg_batch_plan* p, const uint64_t* codes, uint32_t* out_idx, uint16_t* out_dist,
-            hipStream_t stream) {
+            hipStream_t stream, bool timed) {
   if (p->nitems == 0) return BDG_OK;
   hipError_t e = bdg::launch_prep(codes, p->n_total, p->words, p->frags, stream);
   if (e == hipSuccess && p->bgroup) {
@@ -181,7 +183,10 @@ int enqueue(const bdg_batch_plan* p, const uint64_t* codes, uint32_t* out_idx, u
     a.schedule = p->schedule;
     a.bound = p->bgroup ? p->bound : nullptr;
     a.bound_base = p->base;
-    e = bdg::launch_mfma_batched(a, stream);
+    timed = timed && p->ev_start && p->ev_stop;
+    if (timed) e = hipEventRecord(p->ev_start, stream);
+    if (e == hipSuccess) e = bdg::launch_mfma_batched(a, stream);
+    if (e == hipSuccess && timed) e = hipEventRecord(p->ev_stop, stream);
   }
   if (e != hipSuccess) return bdg::api_device_error(e, "batched launch");
   return BDG_OK;
@@ -369,7 +374,16 @@ int bdg_build_knn_batched_plan(const bdg_batch_plan* plan, const uint64_t* codes
   if (plan->nitems && (!codes || !out_idx || !out_dist))
     return bdg::api_error(BDG_EINVAL, "null device pointer");
   (void)hipGetLastError();
-  return enqueue(plan, codes, out_idx, out_dist, reinterpret_cast<hipStream_t>(stream));
+  return enqueue(plan, codes, out_idx, out_dist, reinterpret_cast<hipStream_t>(stream), true);
+}
+
+int bdg_batch_plan_set_timing(bdg_batch_plan* plan, void* start_event, void* stop_event) {
+  if (!plan) return bdg::api_error(BDG_EINVAL, "plan is NULL");
+  if ((start_event == nullptr) != (stop_event == nullptr))
+    return bdg::api_error(BDG_EINVAL, "give both events or neither");
+  plan->ev_start = reinterpret_cast<hipEvent_t>(start_event);
+  plan->ev_stop = reinterpret_cast<hipEvent_t>(stop_event);
+  return BDG_OK;
 }
 
 int bdg_build_knn_batched_graph(bdg_batch_plan* plan, const uint64_t* codes, uint32_t* out_idx,
@@ -386,7 +400,7 @@ int bdg_build_knn_batched_graph(bdg_batch_plan* plan, const uint64_t* codes, uin
   if (!plan->exec) {
     hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return bdg::api_device_error(e, "begin capture");
-    const int st = enqueue(plan, codes, out_idx, out_dist, stream);
+    const int st = enqueue(plan, codes, out_idx, out_dist, stream, false);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(stream, &g);
     if (st != BDG_OK) {

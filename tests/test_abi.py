@@ -197,3 +197,4 @@ def test_bound_group_validation():
         assert call_ex(bits=256, opts=o) == bdg.BDG_EUNSUPPORTED, g
         assert "bound_group" in bdg.last_error()
     assert L.bdg_batch_plan_set_bound(None, 256) == bdg.BDG_EINVAL
+    assert L.bdg_batch_plan_set_timing(None, None, None) == bdg.BDG_EINVAL

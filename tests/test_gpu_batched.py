@@ -287,3 +287,32 @@ def test_autotune_build_keeps_the_graph():
     idx2, dist2 = bdg.build_knn(d, 32)
     g2 = to_np((idx2, dist2))
     assert np.array_equal(g2[0], gi) and np.array_equal(g2[1], gd)
+
+
+def test_plan_timing_events():
+    # events around the persistent kernel of an eager build: a positive
+    # duration, no shorter than nothing and within the whole call; same graph
+    import ctypes
+    import torch
+    rt = ctypes.CDLL("libamdhip64.so")
+    rt.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+    rt.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
+                                       ctypes.c_void_p]
+    rt.hipEventDestroy.argtypes = [ctypes.c_void_p]
+    ev = [ctypes.c_void_p(), ctypes.c_void_p()]
+    for e in ev:
+        assert rt.hipEventCreate(ctypes.byref(e)) == 0
+    codes, offsets = shard_codes([3000, 500, 8000], 256, seed=23)
+    d = dev(codes)
+    plan = bdg.BatchPlan(offsets, 256, 16)
+    ref = to_np(plan.build(d))
+    plan.set_timing(ev[0].value, ev[1].value)
+    got = to_np(plan.build(d))
+    ms = ctypes.c_float()
+    assert rt.hipEventElapsedTime(ctypes.byref(ms), ev[0], ev[1]) == 0
+    assert 0.0 < ms.value < 1000.0
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+    plan.set_timing(None, None)
+    plan.close()
+    for e in ev:
+        rt.hipEventDestroy(e)
