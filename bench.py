@@ -55,6 +55,7 @@ KERNEL_SOURCES = {
     "knn_mfma_sweep_kernel": ["tile_mfma_kern.h", "wave_topk.h", "tile_mfma.hip", "kernels.h"],
     "knn_mfma_batched_kernel": ["tile_mfma_kern.h", "wave_topk.h", "tile_mfma.hip", "kernels.h"],
     "knn_popc_kernel": ["knn_tiles.hip", "wave_topk.h", "kernels.h"],
+    "propagate_kernel": ["propagate.hip", "wave_topk64.h", "kernels.h"],
 }
 CALIB_BYTES = 256 << 20
 
@@ -278,13 +279,17 @@ def recall_leg():
             "search_recall_at_60": {"srp": res["search_srp"], "learned": res["search_learned"]}}
 
 
-def propagation_leg(codes, codes_dev, exact, bits, K, with_oracle, steps=3):
+def propagation_leg(codes, codes_dev, exact, bits, K, with_oracle, workload, steps=3):
     """One round of neighbourhood propagation (Sec. 3.3) on the workload's
     codes, from an inexact graph: the exact graph with half of every row's
     entries replaced by seeded random rows. Reports the kernel time (HIP
     events on the launch stream), recall@K of the input and of the output
-    against the exact graph, the algorithmic bytes of the gathers against the
-    HBM peak, and the oracle on a seeded row sample (parity and rate)."""
+    against the exact graph, the bytes the kernel moves through HBM (from the
+    committed FETCH_SIZE / WRITE_SIZE record of this kernel and workload, if
+    its sources are unchanged) against the HBM peak with the algorithmic
+    gather bytes beside them, and the oracle on a seeded row sample (parity
+    and rate). The kernel is latency-bound (random gathers of lists and
+    codes, most served from L2 and the Infinity Cache)."""
     import torch
     from paper_2102_04656_amd import bdg
     n = exact.shape[0]
@@ -316,10 +321,18 @@ def propagation_leg(codes, codes_dev, exact, bits, K, with_oracle, steps=3):
            "n": n, "K": K, "bits": bits, "ms": ms, "kernel": "propagate_kernel",
            "candidates_per_s": n * cand / (ms * 1e-3),
            "recall_in": recall(in_idx), "recall_out": recall(out[0]),
-           "roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
-                        "frac": achieved / 8000.0, "bytes_per_row": row_bytes,
-                        "note": "algorithmic gather bytes; codes and lists are largely served "
-                                "from L2/MALL"}}
+           "roofline": {"bound": "latency", "achieved": None, "peak": 8000.0, "unit": "GB/s",
+                        "frac": None, "traffic": None,
+                        "algorithmic_bytes_per_row": row_bytes,
+                        "algorithmic_gb_per_s": achieved,
+                        "note": "random gathers of lists and codes; the per-wave hash set "
+                                "gathers each distinct candidate once and most reads hit "
+                                "L2/MALL, so HBM is far from the bound"}}
+    rec = recorded_traffic("propagate_kernel", workload)
+    if rec is not None:
+        hbm = rec["bytes_per_launch"] / (ms * 1e-3) / 1e9
+        res["roofline"].update(achieved=hbm, frac=hbm / 8000.0, traffic=rec["bytes_per_launch"],
+                               traffic_source=f"profiles/traffic__propagate_kernel__{workload}.md")
     if with_oracle:
         import oracle
         rows = np.sort(np.random.default_rng(2102).choice(n, size=256, replace=False))
@@ -754,7 +767,8 @@ def main():
     if args.propagate:
         log("[bench] propagation leg")
         result["propagation"] = propagation_leg(codes, codes_dev, outs[0], bits, K,
-                                                with_oracle=not args.no_cpu_baseline)
+                                                with_oracle=not args.no_cpu_baseline,
+                                                workload=args.workload)
         log(f"[bench] propagation: {result['propagation']['ms']:.2f} ms, recall "
             f"{result['propagation']['recall_in']:.3f} -> {result['propagation']['recall_out']:.3f}")
     if args.dac:
