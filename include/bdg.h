@@ -44,7 +44,9 @@ extern "C" {
 #define BDG_NO_IDX 0xFFFFFFFFu
 #define BDG_NO_DIST 0xFFFFu
 #define BDG_MAX_BITS 1024u
-#define BDG_MAX_K 256u
+#define BDG_MAX_K 1024u     /* builds on the vector-ALU path, list merges */
+#define BDG_MAX_K_TILE 256u /* the matrix-core path, batched plans, divide-and-
+                               conquer, propagation and search */
 
 typedef enum bdg_status {
     BDG_OK = 0,
@@ -137,7 +139,8 @@ typedef struct bdg_knn_opts {
  *   codes   [n][bits/64] uint64, device
  *   n       number of codes (0 is a no-op)
  *   bits    code length, a multiple of 64, at most BDG_MAX_BITS
- *   K       neighbours per row, 1..BDG_MAX_K
+ *   K       neighbours per row, 1..BDG_MAX_K (the matrix-core path takes
+ *           K <= BDG_MAX_K_TILE; path AUTO picks the vector ALUs beyond)
  *   out_idx [n][K] uint32, out_dist [n][K] uint16, device
  * Runs on the default stream and returns after completion. It allocates its
  * workspace itself and, on the matrix-core path, checks the persistent
@@ -265,7 +268,7 @@ int bdg_bkmeans(const uint64_t *codes, uint32_t n, uint32_t bits, const uint32_t
  * exact graph.
  *   codes [n][bits/64], centres [m][bits/64] uint64, device
  *   out_idx [n][K] uint32, out_dist [n][K] uint16, device
- * T in 1..64, K in 1..BDG_MAX_K, m in 1..2^20, coarse_num >= 1. Scratch
+ * T in 1..64, K in 1..BDG_MAX_K_TILE, m in 1..2^20, coarse_num >= 1. Scratch
  * (about n (4 T + 4 + bits/8) bytes) is allocated and freed on `stream`
  * (stream-ordered). Errors as bdg_build_knn_ex; BDG_EUNSUPPORTED for T > 64.
  */
@@ -292,7 +295,7 @@ int bdg_build_knn_dac(const uint64_t *codes, uint32_t n, uint32_t bits, const ui
  * 1 <= N <= P <= 1024, n < 2^31. Visited bitmaps (n/8 bytes per query, in
  * batches of at most 1 GiB) are allocated and freed on `stream`. Errors:
  * BDG_EINVAL (bits, zero sizes, N > P, null pointer), BDG_EUNSUPPORTED
- * (P > 1024, K > BDG_MAX_K, bits > BDG_MAX_BITS, n >= 2^31), BDG_ENOMEM,
+ * (P > 1024, K > BDG_MAX_K_TILE, bits > BDG_MAX_BITS, n >= 2^31), BDG_ENOMEM,
  * BDG_EDEVICE.
  */
 int bdg_graph_search(const uint64_t *codes, uint32_t n, uint32_t bits, const uint32_t *graph,

@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(PKG, "libbdg.so")
 BDG_OK, BDG_EINVAL, BDG_EUNSUPPORTED, BDG_ENOMEM, BDG_EDEVICE = 0, -1, -2, -3, -4
 PATH_AUTO, PATH_POPC, PATH_MFMA = 0, 1, 2
 NO_IDX, NO_DIST = 0xFFFFFFFF, 0xFFFF
-MAX_BITS, MAX_K = 1024, 256
+MAX_BITS, MAX_K, MAX_K_TILE = 1024, 1024, 256
 
 
 class BdgLibraryMissing(ImportError):

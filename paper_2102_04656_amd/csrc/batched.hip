@@ -208,7 +208,7 @@ int bdg_batch_plan_create(const uint64_t* offsets, uint32_t S, uint32_t bits, ui
     return bdg::api_error(BDG_EINVAL, "bits must be a positive multiple of 64 (got %u)", bits);
   if (bits > BDG_MAX_BITS) return bdg::api_error(BDG_EUNSUPPORTED, "bits > %u", BDG_MAX_BITS);
   if (K == 0) return bdg::api_error(BDG_EINVAL, "K must be >= 1");
-  if (K > BDG_MAX_K) return bdg::api_error(BDG_EUNSUPPORTED, "K > %u", BDG_MAX_K);
+  if (K > BDG_MAX_K_TILE) return bdg::api_error(BDG_EUNSUPPORTED, "K > %u", BDG_MAX_K_TILE);
   if (offsets[S] >= 0xFFFFFFFFull)
     return bdg::api_error(BDG_EUNSUPPORTED, "more than 2^32 - 2 rows in all shards");
   const uint32_t words = bits / 64;

@@ -434,7 +434,7 @@ int bdg_propagate(const uint64_t* codes, uint32_t n, uint32_t bits, uint32_t K,
     return set_error(BDG_EINVAL, "bits must be a positive multiple of 64 (got %u)", bits);
   if (bits > BDG_MAX_BITS) return set_error(BDG_EUNSUPPORTED, "bits > %u", BDG_MAX_BITS);
   if (K == 0) return set_error(BDG_EINVAL, "K must be >= 1");
-  if (K > BDG_MAX_K) return set_error(BDG_EUNSUPPORTED, "K > %u", BDG_MAX_K);
+  if (K > BDG_MAX_K_TILE) return set_error(BDG_EUNSUPPORTED, "K > %u", BDG_MAX_K_TILE);
   if (n == 0xFFFFFFFFu) return set_error(BDG_EUNSUPPORTED, "n must be < 2^32 - 1");
   if (n == 0) return BDG_OK;
   if (!codes || !in_idx || !out_idx || !out_dist)
@@ -506,7 +506,7 @@ int bdg_build_knn_dac(const uint64_t* codes, uint32_t n, uint32_t bits, const ui
   if (bits > BDG_MAX_BITS) return set_error(BDG_EUNSUPPORTED, "bits > %u", BDG_MAX_BITS);
   if (K == 0 || m == 0 || T == 0 || coarse_num == 0)
     return set_error(BDG_EINVAL, "K, m, T and coarse_num must be >= 1");
-  if (K > BDG_MAX_K) return set_error(BDG_EUNSUPPORTED, "K > %u", BDG_MAX_K);
+  if (K > BDG_MAX_K_TILE) return set_error(BDG_EUNSUPPORTED, "K > %u", BDG_MAX_K_TILE);
   if (T > 64) return set_error(BDG_EUNSUPPORTED, "T > 64");
   if (m > (1u << 20)) return set_error(BDG_EUNSUPPORTED, "m > 2^20");
   if (n == 0xFFFFFFFFu) return set_error(BDG_EUNSUPPORTED, "n must be < 2^32 - 1");
@@ -549,7 +549,7 @@ int bdg_graph_search(const uint64_t* codes, uint32_t n, uint32_t bits, const uin
   if (K == 0 || d == 0 || S == 0 || P == 0 || N == 0)
     return set_error(BDG_EINVAL, "K, d, S, P and N must be >= 1");
   if (N > P) return set_error(BDG_EINVAL, "N must be <= P");
-  if (P > 1024 || K > BDG_MAX_K) return set_error(BDG_EUNSUPPORTED, "P > 1024 or K > %u", BDG_MAX_K);
+  if (P > 1024 || K > BDG_MAX_K_TILE) return set_error(BDG_EUNSUPPORTED, "P > 1024 or K > %u", BDG_MAX_K_TILE);
   if (n == 0xFFFFFFFFu || n > 0x7FFFFFFFu) return set_error(BDG_EUNSUPPORTED, "n must be < 2^31");
   if (nq == 0 || n == 0) return BDG_OK;
   if (!codes || !graph || !feats || !q_codes || !q_feats || !entries || !out_idx || !out_dist)

@@ -153,7 +153,7 @@ static size_t lds_bytes(uint32_t words, uint32_t K) {
 static constexpr size_t kLdsMax = 160 * 1024;
 
 bool tile_supported(int path, uint32_t words, uint32_t K) {
-  if (words < 1 || words > 16 || K < 1 || K > 256) return false;
+  if (words < 1 || words > 16 || K < 1 || K > 1024) return false;
   if (path != kPathPopc) return false;
   return lds_bytes(words, K) <= kLdsMax;
 }
@@ -183,7 +183,9 @@ template <int W>
 static hipError_t launch_nr(int path, const TileArgs& a, hipStream_t stream) {
   if (a.K <= 64) return launch_w<W, 1>(path, a, stream);
   if (a.K <= 128) return launch_w<W, 2>(path, a, stream);
-  return launch_w<W, 4>(path, a, stream);
+  if (a.K <= 256) return launch_w<W, 4>(path, a, stream);
+  if (a.K <= 512) return launch_w<W, 8>(path, a, stream);
+  return launch_w<W, 16>(path, a, stream);
 }
 
 hipError_t launch_tile(int path, const TileArgs& a, hipStream_t stream) {

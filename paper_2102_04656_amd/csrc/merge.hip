@@ -105,8 +105,14 @@ hipError_t launch_merge(const uint32_t* in_idx, const uint16_t* in_dist, uint32_
   else if (K <= 128)
     hipLaunchKernelGGL(merge_lists_kernel<2>, grid, dim3(256), 0, stream, in_idx, in_dist, n, L,
                        K_in, K, out_idx, out_dist, dedup);
-  else
+  else if (K <= 256)
     hipLaunchKernelGGL(merge_lists_kernel<4>, grid, dim3(256), 0, stream, in_idx, in_dist, n, L,
+                       K_in, K, out_idx, out_dist, dedup);
+  else if (K <= 512)
+    hipLaunchKernelGGL(merge_lists_kernel<8>, grid, dim3(256), 0, stream, in_idx, in_dist, n, L,
+                       K_in, K, out_idx, out_dist, dedup);
+  else
+    hipLaunchKernelGGL(merge_lists_kernel<16>, grid, dim3(256), 0, stream, in_idx, in_dist, n, L,
                        K_in, K, out_idx, out_dist, dedup);
   return hipGetLastError();
 }

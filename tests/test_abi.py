@@ -51,7 +51,8 @@ def call_ex(n=10, bits=128, K=4, codes=FAKE, oi=FAKE, od=FAKE, opts=None):
     (dict(bits=100), bdg.BDG_EINVAL),
     (dict(bits=1088), bdg.BDG_EUNSUPPORTED),
     (dict(K=0), bdg.BDG_EINVAL),
-    (dict(K=257), bdg.BDG_EUNSUPPORTED),
+    (dict(K=1025), bdg.BDG_EUNSUPPORTED),
+    (dict(K=257, opts=bdg.make_opts(path=bdg.PATH_MFMA)), bdg.BDG_EUNSUPPORTED),
     (dict(n=0xFFFFFFFF), bdg.BDG_EUNSUPPORTED),
     (dict(codes=None), bdg.BDG_EINVAL),
     (dict(oi=None), bdg.BDG_EINVAL),
@@ -151,7 +152,8 @@ def test_merge_rejects_bad_arguments():
     assert L.bdg_merge_lists(FAKE, FAKE, 10, 0, 4, 4, FAKE, FAKE, None) == bdg.BDG_EINVAL
     assert L.bdg_merge_lists(FAKE, FAKE, 10, 2, 0, 4, FAKE, FAKE, None) == bdg.BDG_EINVAL
     assert L.bdg_merge_lists(FAKE, FAKE, 10, 2, 4, 0, FAKE, FAKE, None) == bdg.BDG_EINVAL
-    assert L.bdg_merge_lists(FAKE, FAKE, 10, 2, 4, 300, FAKE, FAKE, None) == bdg.BDG_EUNSUPPORTED
+    assert L.bdg_merge_lists(FAKE, FAKE, 10, 2, 4, 1025, FAKE, FAKE, None) == bdg.BDG_EUNSUPPORTED
+    assert L.bdg_merge_lists(FAKE, FAKE, 10, 2, 1025, 4, FAKE, FAKE, None) == bdg.BDG_EUNSUPPORTED
     assert L.bdg_merge_lists(None, FAKE, 10, 2, 4, 4, FAKE, FAKE, None) == bdg.BDG_EINVAL
     assert L.bdg_merge_lists(None, None, 0, 2, 4, 4, None, None, None) == bdg.BDG_OK
 

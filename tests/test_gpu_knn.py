@@ -165,6 +165,23 @@ def test_admission_bounds_on_ties():
                     f"repeated K={K}")
 
 
+# ------------------------------------------------- long lists (K > 256)
+
+@pytest.mark.parametrize("n,bits,K,col_block", [
+    (1500, 256, 300, 0), (1200, 128, 600, 500), (1100, 64, 1000, 0), (2500, 512, 1024, 1000),
+    (700, 192, 1024, 0),  # K > n - 1: padded rows
+])
+def test_long_lists_on_the_vector_alus(n, bits, K, col_block):
+    # K up to 1024 runs on the vector-ALU path (path AUTO picks it beyond the
+    # matrix-core tile's 256), with per-column-block lists merged when the
+    # columns are split
+    codes = datagen.clustered_codes(n, bits, max(2, n // 100), 0.2, seed=n + K)
+    want = oracle.knn_rows(codes, K)
+    print(f"[long lists] n={n} bits={bits} K={K} col_block={col_block}", flush=True)
+    assert_same(gpu_knn(codes, K, POPC, col_block=col_block), want, f"K={K}")
+    assert_same(gpu_knn(codes, K, bdg.PATH_AUTO), want, f"K={K} auto")
+
+
 # ------------------------------------------------------ named workloads
 
 def test_clustered_20k_128b_k32_full():
@@ -248,7 +265,8 @@ def test_merge_golden():
     assert_same(got, (out_idx, out_dist), "merge golden")
 
 
-@pytest.mark.parametrize("K_in,K", [(16, 16), (64, 32), (100, 100), (40, 128), (256, 256)])
+@pytest.mark.parametrize("K_in,K", [(16, 16), (64, 32), (100, 100), (40, 128), (256, 256),
+                                    (300, 500), (700, 1024)])
 def test_merge_api_with_duplicates(K_in, K):
     import torch
     codes = datagen.clustered_codes(2000, 128, 25, 0.15, seed=K_in + K)
