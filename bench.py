@@ -604,6 +604,7 @@ def time_build(w, workload, path, steps, warmup, other_steps, other_warmup, othe
     schedule, tuned = 0, None
     if autotune:
         log(f"[bench] {workload}: autotuning the build schedule")
+        os.environ.setdefault("BDG_AUTOTUNE_LOG", "1")  # one stderr line per candidate
         t0 = time.perf_counter()
         o, rep = bdg.autotune_build(codes_dev, K, bits=bits, row_block=row_block)
         torch.cuda.synchronize()

@@ -13,7 +13,9 @@
 // Tuned single builds are remembered per (code length, K, size bucket) for
 // the process, and appended as one JSON object per line to the file named by
 // BDG_AUTOTUNE_CACHE (which is read back on first use), so that later builds
-// with path AUTO and no explicit column block take the tuned schedule.
+// with path AUTO and no explicit column block take the tuned schedule. With
+// BDG_AUTOTUNE_LOG set, every candidate's time goes to stderr as it is taken
+// (a tuning run over large inputs takes minutes).
 #include <hip/hip_runtime.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -196,6 +198,11 @@ int bdg_autotune_build(const uint64_t* codes, uint32_t n, uint32_t bits, uint32_
                                 stream, 2, &c.ms);
     if (st != BDG_OK) return -2 - st;
     ok.push_back(c);
+    if (getenv("BDG_AUTOTUNE_LOG")) {
+      fprintf(stderr, "[autotune] path %d col_block %u schedule %d bound_group %u: %.3f ms\n",
+              c.path, c.col_block, c.schedule, c.bound_group, c.ms);
+      fflush(stderr);
+    }
     return (long)ok.size() - 1;
   };
   Cand best{BDG_PATH_MFMA, 262144u, 0, BDG_BOUND_GROUP_DEFAULT, 0.f};
@@ -311,6 +318,11 @@ int bdg_autotune_batched(bdg_batch_plan* plan, const uint64_t* codes, uint32_t* 
                           stream, 1, &c.ms);
       if (st != BDG_OK) return;
       ok.push_back(c);
+      if (getenv("BDG_AUTOTUNE_LOG")) {
+        fprintf(stderr, "[autotune] order %d schedule %d bound_group %u: %.3f ms\n", c.order,
+                c.schedule, c.bound_group, c.ms);
+        fflush(stderr);
+      }
       if (c.ms < ok[best].ms) best = ok.size() - 1;
     }
     if (!ok.empty()) cur = ok[best];
