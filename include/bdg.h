@@ -110,15 +110,15 @@ typedef struct bdg_knn_opts {
 
 /* Admission bounds (matrix-core path). Before the exhaustive search every row
  * gets an upper bound on its K-th neighbour distance: the K-th smallest
- * distance to the other members of its group and of the group of its
- * second-nearest pivot, where pivots are every bound_group-th row of the
- * partition and each row joins its nearest pivot's group. Any K other rows of the partition bound the final K-th distance from
- * above, so admitting only candidates at most the bound while a row's list is
- * not full leaves the graph unchanged; it spares the admissions of far
- * candidates seen before the row's own cluster (the first reduce of Sec. 3.2
- * searches a partition exhaustively, in input order). Costs about
- * n * n / bound_group pair distances and (bits / 8 + 14) n bytes of
- * workspace. */
+ * distance to the other members of its group and of the groups of its second-
+ * and third-nearest pivots, where pivots are every bound_group-th row of the
+ * partition and each row joins its nearest pivot's group. Any K other rows of
+ * the partition bound the final K-th distance from above, so admitting only
+ * candidates at most the bound while a row's list is not full leaves the graph
+ * unchanged; it spares the admissions of far candidates seen before the row's
+ * own cluster (the first reduce of Sec. 3.2 searches a partition
+ * exhaustively, in input order). Costs about n * n / bound_group pair
+ * distances and (bits / 8 + 36) n bytes of workspace. */
 #define BDG_BOUND_OFF 1u
 #define BDG_BOUND_GROUP_DEFAULT 256u
 #define BDG_BOUND_GROUP_MIN 16u
@@ -496,14 +496,19 @@ int bdg_gemm_nt_bf16(const uint16_t *A, uint32_t lda, const uint16_t *B, uint32_
  * and every candidate's time. With BDG_AUTOTUNE_CACHE set, each choice is
  * appended to that file as one JSON line (read back by later processes).
  *
- * bdg_autotune_build: candidates = matrix-core tile with column blocks of
- *   65536 / 131072 / 262144 columns, and the vector-ALU tile; writes the
- *   winner into opts->path and opts->col_block (opts->row_block is used as
- *   given) and remembers it for (bits, K, floor(log2 n)), so later calls with
- *   path AUTO and col_block 0 take it. Runs the build several times into
- *   out_idx/out_dist (device, [n][K]); allocates a workspace for the duration.
- * bdg_autotune_batched: candidates = the two work orders; keeps the faster in
- *   the plan.
+ * bdg_autotune_build: a coordinate search from the defaults over the
+ *   matrix-core tile's column block (131072 / 262144 / 524288 columns), tile
+ *   schedule (BDG_SCHEDULE_*) and admission-bound group (256, off, 128, 512,
+ *   64), then the vector-ALU tile; writes the winner into opts->path,
+ *   opts->col_block, opts->tile_schedule and opts->bound_group
+ *   (opts->row_block is used as given) and remembers it for (bits, K,
+ *   floor(log2 n)), so later calls with path AUTO and col_block 0 take it.
+ *   Runs the build several times into out_idx/out_dist (device, [n][K]);
+ *   allocates a workspace for the duration.
+ * bdg_autotune_batched: the same search over the work order, the tile
+ *   schedule and the admission-bound group; keeps the fastest in the plan.
+ * With BDG_AUTOTUNE_LOG set, every candidate's time is printed to stderr as
+ * it is taken.
  */
 int bdg_autotune_build(const uint64_t *codes, uint32_t n, uint32_t bits, uint32_t K,
                        uint32_t *out_idx, uint16_t *out_dist, bdg_knn_opts *opts, void *stream,

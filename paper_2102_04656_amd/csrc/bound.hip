@@ -13,12 +13,12 @@
 // every `group` rows of the partition (input order, so a strided sample), each
 // row joining the group of its nearest pivot (ties to the lower pivot), and
 // the bound is the K-th smallest distance to up to `cap` other members of its
-// own group and up to `cap` members of the group of its second-nearest pivot
-// (a cluster larger than the group size holds several pivots, and two groups
-// cover more of it; the binary k-means of Sec. 3.2 groups similar codes the
-// same way and also lets a record join more than one partition; here the
-// grouping only bounds an exact search). Where the two groups have fewer than
-// K other members the row gets no bound (0xFFFF).
+// own group and up to `cap` members of each of the groups of its second- and
+// third-nearest pivots (a cluster larger than the group size holds several
+// pivots, and three groups cover more of it; the binary k-means of Sec. 3.2
+// groups similar codes the same way and also lets a record join more than one
+// partition; here the grouping only bounds an exact search). Where the three
+// groups have fewer than K other members the row gets no bound (0xFFFF).
 //
 // Exactness: every candidate of the row's true top K lies at a distance of at
 // most the true K-th distance, hence at most the bound, so a tile that admits
@@ -55,6 +55,7 @@ struct BK {
   const uint32_t* pseg;  // nullptr: its pivots [0, npiv)
   uint32_t* nearest;  // [total] group of row base + i
   uint32_t* second;   // [total] group of its second-nearest pivot (= nearest if none)
+  uint32_t* third;    // [total] group of its third-nearest pivot (= nearest if none)
   uint32_t* offs;     // [npiv + 1] group sizes, then offsets
   uint32_t* cursor;   // [npiv]
   uint32_t* members;  // [total] rows (relative) in group order
@@ -105,16 +106,20 @@ __global__ __launch_bounds__(256) void nearest_pivot_kernel(BK a) {
   uint64_t q[W];
 #pragma unroll
   for (int w = 0; w < W; ++w) q[w] = a.codes[(size_t)r * W + w];
-  // nearest (b1, j1) and second-nearest (b2, j2) pivot, ties to the lower one
+  // the three nearest pivots (b1, j1) <= (b2, j2) <= (b3, j3), ties to the
+  // lower pivot
   uint32_t b1 = 0xFFFFFFFFu, j1 = 0, b2 = 0xFFFFFFFFu, j2 = 0xFFFFFFFFu, p0;
-#define BDG_OFFER(dv, jv)                              \
-  do {                                                 \
-    const uint32_t d_ = (dv), jj_ = (jv);              \
-    const bool lt1_ = d_ < b1, lt2_ = d_ < b2;         \
-    b2 = lt1_ ? b1 : (lt2_ ? d_ : b2);                 \
-    j2 = lt1_ ? j1 : (lt2_ ? jj_ : j2);                \
-    b1 = lt1_ ? d_ : b1;                               \
-    j1 = lt1_ ? jj_ : j1;                              \
+  uint32_t b3 = 0xFFFFFFFFu, j3 = 0xFFFFFFFFu;
+#define BDG_OFFER(dv, jv)                                          \
+  do {                                                             \
+    const uint32_t d_ = (dv), jj_ = (jv);                          \
+    const bool lt1_ = d_ < b1, lt2_ = d_ < b2, lt3_ = d_ < b3;     \
+    b3 = lt2_ ? b2 : (lt3_ ? d_ : b3);                             \
+    j3 = lt2_ ? j2 : (lt3_ ? jj_ : j3);                            \
+    b2 = lt1_ ? b1 : (lt2_ ? d_ : b2);                             \
+    j2 = lt1_ ? j1 : (lt2_ ? jj_ : j2);                            \
+    b1 = lt1_ ? d_ : b1;                                           \
+    j1 = lt1_ ? jj_ : j1;                                          \
   } while (0)
   const uint32_t s0 = __builtin_amdgcn_readfirstlane(s);
   if (__ballot(s != s0) == 0) {
@@ -127,14 +132,17 @@ __global__ __launch_bounds__(256) void nearest_pivot_kernel(BK a) {
     uint32_t j = 0;
     if (np <= kKeyPivots) {
       // (distance, pivot) as one key, distance << 21 | pivot (distances are at
-      // most 1024): the two smallest keys by min / max; four pivots per step,
-      // their loads issued together
-      uint32_t k1 = 0xFFFFFFFFu, k2 = 0xFFFFFFFFu;
+      // most 1024): the three smallest keys by min / max; four pivots per
+      // step, their loads issued together
+      uint32_t k1 = 0xFFFFFFFFu, k2 = 0xFFFFFFFFu, k3 = 0xFFFFFFFFu;
 #define BDG_PUT(dv, jv)                                   \
   do {                                                    \
     const uint32_t k_ = ((dv) << kKeyShift) | (jv);       \
-    k2 = min(k2, max(k1, k_));                            \
+    const uint32_t t1_ = max(k1, k_);                     \
     k1 = min(k1, k_);                                     \
+    const uint32_t t2_ = max(k2, t1_);                    \
+    k2 = min(k2, t1_);                                    \
+    k3 = min(k3, t2_);                                    \
   } while (0)
       for (; j + 4 <= np; j += 4) {
         const uint64_t* c = pc + (size_t)j * stride;
@@ -149,6 +157,7 @@ __global__ __launch_bounds__(256) void nearest_pivot_kernel(BK a) {
 #undef BDG_PUT
       j1 = k1 & (kKeyPivots - 1);
       j2 = k2 == 0xFFFFFFFFu ? 0xFFFFFFFFu : (k2 & (kKeyPivots - 1));
+      j3 = k3 == 0xFFFFFFFFu ? 0xFFFFFFFFu : (k3 & (kKeyPivots - 1));
     } else {
       for (; j < np; ++j) BDG_OFFER(ham_to<W>(q, pc + (size_t)j * stride), j);
     }
@@ -163,6 +172,7 @@ __global__ __launch_bounds__(256) void nearest_pivot_kernel(BK a) {
     const uint32_t g = p0 + j1;
     a.nearest[i] = g;
     a.second[i] = j2 == 0xFFFFFFFFu ? g : p0 + j2;
+    a.third[i] = j3 == 0xFFFFFFFFu ? g : p0 + j3;
     atomicAdd(&a.offs[g + 1], 1u);
   }
 }
@@ -178,14 +188,15 @@ __global__ __launch_bounds__(256) void gather_pivots_kernel(const uint64_t* __re
   out[t] = codes[((size_t)base + j * group) * words + w];
 }
 
-// Nearest and second-nearest pivot from the tile's two-element lists
-// ((distance, pivot) order; a missing second entry when there is one pivot).
-__global__ __launch_bounds__(256) void top2_kernel(BK a, const uint32_t* __restrict__ top) {
+// The three nearest pivots from the tile's three-element lists ((distance,
+// pivot) order; missing entries when there are fewer pivots).
+__global__ __launch_bounds__(256) void top3_kernel(BK a, const uint32_t* __restrict__ top) {
   const uint32_t i = blockIdx.x * 256 + threadIdx.x;
   if (i >= a.total) return;
-  const uint32_t g = top[2 * (size_t)i], g2 = top[2 * (size_t)i + 1];
+  const uint32_t g = top[3 * (size_t)i], g2 = top[3 * (size_t)i + 1], g3 = top[3 * (size_t)i + 2];
   a.nearest[i] = g;
   a.second[i] = g2 == 0xFFFFFFFFu ? g : g2;
+  a.third[i] = g3 == 0xFFFFFFFFu ? g : g3;
   atomicAdd(&a.offs[g + 1], 1u);
 }
 
@@ -230,7 +241,8 @@ __global__ __launch_bounds__(256) void scatter_group_kernel(BK a) {
 
 // Four rows per wave (16 lanes each, kBoundSlots slots), at consecutive
 // positions of the group order: the row against up to cap + 1 members of its
-// group (itself skipped) and up to cap members of its second group, distances
+// group (itself skipped) and up to cap members of each of its second and third
+// groups (each group once), distances
 // counted in the slot's histogram in LDS; the bound is the smallest distance
 // with at least K members at or below it. Several rows per wave keep several
 // chains of dependent loads (position -> row -> groups -> members) in flight.
@@ -245,10 +257,10 @@ __global__ __launch_bounds__(64 * kBoundWaves) void group_bound_kernel(BK a) {
   const uint32_t pos = (blockIdx.x * kBoundWaves + wave) * kBoundSlots + slot;
   const bool live = pos < a.total;
   for (uint32_t x = sub; x < nb; x += 16) hist[x] = 0;
-  uint32_t i = 0, m = 0, m2 = 0, gb = 0, gb2 = 0;
+  uint32_t i = 0, m = 0, m2 = 0, m3 = 0, gb = 0, gb2 = 0, gb3 = 0;
   if (live) {
     i = a.members[pos];
-    const uint32_t g = a.nearest[i], g2 = a.second[i];
+    const uint32_t g = a.nearest[i], g2 = a.second[i], g3 = a.third[i];
     gb = a.offs[g];
     const uint32_t s1 = a.offs[g + 1] - gb;
     m = s1 < a.cap + 1 ? s1 : a.cap + 1;
@@ -257,19 +269,24 @@ __global__ __launch_bounds__(64 * kBoundWaves) void group_bound_kernel(BK a) {
       const uint32_t s2 = a.offs[g2 + 1] - gb2;
       m2 = s2 < a.cap ? s2 : a.cap;
     }
+    if (g3 != g && g3 != g2) {
+      gb3 = a.offs[g3];
+      const uint32_t s3 = a.offs[g3 + 1] - gb3;
+      m3 = s3 < a.cap ? s3 : a.cap;
+    }
   }
   uint64_t q[W];
 #pragma unroll
   for (int w = 0; w < W; ++w) q[w] = live ? a.gcodes[(size_t)pos * W + w] : 0ull;
   wave_fence_sync();  // the cleared histograms before any count
   const uint32_t self = pos - gb;  // the row's place in its group (it is a member)
-  for (uint32_t t = sub; t < m + m2; t += 16) {
-    const uint32_t p = t < m ? gb + t : gb2 + (t - m);
+  for (uint32_t t = sub; t < m + m2 + m3; t += 16) {
+    const uint32_t p = t < m ? gb + t : (t < m + m2 ? gb2 + (t - m) : gb3 + (t - m - m2));
     if (t != self) atomicAdd(&hist[ham_to<W>(q, a.gcodes + (size_t)p * W)], 1u);
   }
   wave_fence_sync();
   // the row is a member of its own group only
-  const uint32_t others = m + m2 - (self < m ? 1u : 0u);
+  const uint32_t others = m + m2 + m3 - (self < m ? 1u : 0u);
   const bool want = live && others >= a.K;
   // prefix sums over the slot's 16 lanes of their bins' counts
   const uint32_t per = (nb + 15) / 16;
@@ -306,14 +323,14 @@ hipError_t launch_words(const BK& k, const BoundArgs& a, hipStream_t stream) {
   const dim3 rows((k.total + 255) / 256);
   if (a.rect_scratch && !a.seg) {
     // every row against every pivot on the matrix cores: a rectangular tile
-    // with two-element lists (rows = the codes, columns = the pivots)
+    // with three-element lists (rows = the codes, columns = the pivots)
     char* p = static_cast<char*>(a.rect_scratch);
     uint64_t* pcodes = reinterpret_cast<uint64_t*>(p);
     p += align256((size_t)k.npiv * W * 8);
     void* pfrags = p;
     p += align256(prep_bytes(k.npiv, W));
     uint32_t* top = reinterpret_cast<uint32_t*>(p);
-    p += align256((size_t)k.total * 8);
+    p += align256((size_t)k.total * 12);
     uint16_t* tdist = reinterpret_cast<uint16_t*>(p);
     hipLaunchKernelGGL(gather_pivots_kernel, dim3((unsigned)(((size_t)k.npiv * W + 255) / 256)),
                        dim3(256), 0, stream, k.codes, k.base, k.group, k.npiv, (uint32_t)W, pcodes);
@@ -324,7 +341,7 @@ hipError_t launch_words(const BK& k, const BoundArgs& a, hipStream_t stream) {
     r.frags = pfrags;
     r.words = W;
     r.bits = k.bits;
-    r.K = 2;
+    r.K = 3;
     r.idx_bits = run_idx_bits(k.bits);
     r.row0 = k.base;
     r.nrows = k.total;
@@ -336,7 +353,7 @@ hipError_t launch_words(const BK& k, const BoundArgs& a, hipStream_t stream) {
     r.rect = 1;
     e = launch_mfma_run(r, stream);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(top2_kernel, rows, dim3(256), 0, stream, k, top);
+    hipLaunchKernelGGL(top3_kernel, rows, dim3(256), 0, stream, k, top);
   } else {
     hipLaunchKernelGGL(nearest_pivot_kernel<W>, rows, dim3(256), 0, stream, k);
   }
@@ -355,9 +372,9 @@ hipError_t launch_words(const BK& k, const BoundArgs& a, hipStream_t stream) {
 }  // namespace
 
 size_t bound_rect_bytes(uint32_t total, uint32_t words, uint32_t npiv) {
-  if (!run_supported(npiv, words, 2)) return 0;
+  if (!run_supported(npiv, words, 3)) return 0;
   return align256((size_t)npiv * words * 8) + align256(prep_bytes(npiv, words)) +
-         align256((size_t)total * 8) + align256((size_t)total * 4);
+         align256((size_t)total * 12) + align256((size_t)total * 6);
 }
 
 uint32_t bound_pivots(uint32_t rows, uint32_t group) {
@@ -365,7 +382,7 @@ uint32_t bound_pivots(uint32_t rows, uint32_t group) {
 }
 
 size_t bound_scratch_bytes(uint32_t total, uint32_t words, uint32_t npiv) {
-  return align256((size_t)total * 4) * 3 + align256(((size_t)npiv + 1) * 4) +
+  return align256((size_t)total * 4) * 4 + align256(((size_t)npiv + 1) * 4) +
          align256((size_t)npiv * 4) + align256((size_t)total * words * 8);
 }
 
@@ -391,6 +408,8 @@ hipError_t launch_bounds_pass(const BoundArgs& a, hipStream_t stream) {
   k.members = reinterpret_cast<uint32_t*>(p);
   p += align256((size_t)a.total * 4);
   k.second = reinterpret_cast<uint32_t*>(p);
+  p += align256((size_t)a.total * 4);
+  k.third = reinterpret_cast<uint32_t*>(p);
   p += align256((size_t)a.total * 4);
   k.offs = reinterpret_cast<uint32_t*>(p);
   p += align256(((size_t)a.npiv + 1) * 4);

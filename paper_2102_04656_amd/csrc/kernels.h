@@ -158,8 +158,9 @@ hipError_t launch_mfma_sweep(const SweepArgs& a, hipStream_t stream);
 // segment). Segment s has pivots = its rows seg[s] + j * group, j <
 // ceil(size / group), numbered from pseg[s]; every row joins the group of its
 // nearest pivot, and its bound is the K-th smallest distance to up to `cap`
-// other members of that group and up to `cap` members of the group of its
-// second-nearest pivot, or 0xFFFF where those are fewer than K. Any K other rows of the segment bound the K-th distance of the
+// other members of that group and up to `cap` members of each of the groups
+// of its second- and third-nearest pivots, or 0xFFFF where those are fewer
+// than K. Any K other rows of the segment bound the K-th distance of the
 // graph row from above, so a tile that admits only candidates at most the
 // bound while a list is not full still computes the exact graph.
 struct BoundArgs {

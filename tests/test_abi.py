@@ -101,10 +101,10 @@ def test_workspace_size():
     ws0 = bdg.bdg_build_knn_workspace_size(n, 128, 64, o)
     assert ws0 == a256(((n + 15) // 16 * 16 + 256) * 128) + a256(1174 * 4)
     # with them (the default, pivot groups of 256 rows): the bounds (2 bytes a
-    # row), then nearest and second-nearest pivots and group members (4 bytes a
-    # row each), group offsets and cursors (4 bytes a pivot each, one more
-    # offset) and the codes in group order; then, for the pivot search on the
-    # matrix cores, the pivots' codes and operand fragments and every row's two
+    # row), then the three nearest pivots and group members (4 bytes a row
+    # each), group offsets and cursors (4 bytes a pivot each, one more offset)
+    # and the codes in group order; then, for the pivot search on the matrix
+    # cores, the pivots' codes and operand fragments and every row's three
     # nearest pivots (4 + 2 bytes each)
     for group in (0, 256, 100, 16):
         g = group or 256
@@ -112,9 +112,9 @@ def test_workspace_size():
         o = bdg.make_opts(path=bdg.PATH_MFMA, bound_group=group)
         ws = bdg.bdg_build_knn_workspace_size(n, 128, 64, o)
         frags = ((npiv + 15) // 16 * 16 + 256) * 128
-        assert ws == ws0 + a256(2 * n) + 3 * a256(4 * n) + a256(4 * (npiv + 1)) + \
+        assert ws == ws0 + a256(2 * n) + 4 * a256(4 * n) + a256(4 * (npiv + 1)) + \
             a256(4 * npiv) + a256(16 * n) + \
-            a256(16 * npiv) + a256(frags) + a256(8 * n) + a256(4 * n), group
+            a256(16 * npiv) + a256(frags) + a256(12 * n) + a256(6 * n), group
     # n <= K + 1: no row has more candidates than it keeps, no bounds
     o = bdg.make_opts(path=bdg.PATH_MFMA)
     assert bdg.bdg_build_knn_workspace_size(65, 128, 64, o) == \
