@@ -272,6 +272,28 @@ int bdg_bkmeans(const uint64_t *codes, uint32_t n, uint32_t bits, const uint32_t
  * (about n (4 T + 4 + bits/8) bytes) is allocated and freed on `stream`
  * (stream-ordered). Errors as bdg_build_knn_ex; BDG_EUNSUPPORTED for T > 64.
  */
+/*
+ * Exact Hamming kNN of query codes against a base set: the exhaustive search
+ * of one partition's queries against its base records (Sec. 3.2, the first
+ * reduce with queries and base kept apart) and the binary linear search used
+ * as ground truth for queries outside the base (Sec. 4.5). Row q = the first K
+ * of (ham(queries[q], base[j]), j) over every base row j, in (distance, index)
+ * order, padded with BDG_NO_IDX / BDG_NO_DIST when nb < K; no row is left out
+ * (a query equal to base row j finds j at distance 0). Runs on the matrix-core
+ * tile in its rectangular mode.
+ *   queries [nq][bits/64], base [nb][bits/64] uint64, device
+ *   out_idx [nq][K] uint32, out_dist [nq][K] uint16, device
+ * K in 1..64; nb below 2^(32 - bits needed for a distance) (4,194,303 at 512
+ * bits). A workspace of the base's operand fragments (about nb * bits bytes) is
+ * allocated and freed on `stream` (stream-ordered); enqueued on `stream`.
+ * Errors: BDG_EINVAL (bits, K = 0, null pointer), BDG_EUNSUPPORTED (bits >
+ * BDG_MAX_BITS, K > 64, nb too large), BDG_ENOMEM, BDG_EDEVICE. nq = 0 is a
+ * no-op.
+ */
+int bdg_hamming_knn(const uint64_t *queries, uint32_t nq, const uint64_t *base, uint32_t nb,
+                    uint32_t bits, uint32_t K, uint32_t *out_idx, uint16_t *out_dist,
+                    void *stream);
+
 int bdg_build_knn_dac(const uint64_t *codes, uint32_t n, uint32_t bits, const uint64_t *centres,
                       uint32_t m, uint32_t T, uint32_t coarse_num, uint32_t K, uint32_t *out_idx,
                       uint16_t *out_dist, void *stream);

@@ -21,6 +21,8 @@ Contents
                              top-K of a row's list and its neighbours' lists.
   * ``propagate_filtered``-- the same with the paper's propagation filter
                              (Sec. 3.6 (3)) applied to the second floor.
+  * ``knn_rect``          -- queries against a separate base set (the same
+                             definition with no row left out).
   * ``bkmeans``, ``nearest_centres``, ``dac_graph`` -- the single-pass
                              divide-and-conquer (Sec. 3.2): binary centres,
                              budgeted multi-assignment, partition search.
@@ -335,6 +337,21 @@ def nearest_centres(codes: np.ndarray, centres: np.ndarray, T: int):
     m = D.shape[1]
     order = np.lexsort((np.broadcast_to(np.arange(m), D.shape), D), axis=1)[:, :T]
     return order.astype(np.uint32), np.take_along_axis(D, order, axis=1).astype(np.uint16)
+
+
+def knn_rect(queries: np.ndarray, base: np.ndarray, K: int):
+    """Exact kNN of query codes against a base set (the exhaustive search of a
+    partition's queries against its base records, Sec. 3.2; the binary linear
+    search of Sec. 4.5): row q = the first K of (ham(q, b_j), j) over every
+    base row j, ascending, padded with (NO_IDX, NO_DIST); no row left out."""
+    nq = np.asarray(queries).shape[0]
+    oi = np.full((nq, K), NO_IDX, dtype=np.uint32)
+    od = np.full((nq, K), NO_DIST, dtype=np.uint16)
+    if nq and np.asarray(base).shape[0]:
+        i, d = nearest_centres(queries, base, K)
+        oi[:, :i.shape[1]] = i
+        od[:, :d.shape[1]] = d
+    return oi, od
 
 
 def dac_graph(codes: np.ndarray, centres: np.ndarray, T: int, coarse_num: int, K: int,

@@ -127,6 +127,7 @@ _SIGS = {
     "bdg_propagate": [_p, _u32, _u32, _u32, _p, _p, _p, _p],
     "bdg_bkmeans": [_p, _u32, _u32, _p, _u32, _p, _u32, _u32, _p, _p],
     "bdg_build_knn_dac": [_p, _u32, _u32, _p, _u32, _u32, _u32, _u32, _p, _p, _p],
+    "bdg_hamming_knn": [_p, _u32, _p, _u32, _u32, _u32, _p, _p, _p],
     "bdg_graph_search": [_p, _u32, _u32, _p, _u32, _p, _u32, _p, _p, _p, _u32, _p, _u32, _u32,
                          _u32, _p, _p, _p, _p],
     "bdg_batch_plan_create": [_p, _u32, _u32, _u32, _p, _p],
@@ -324,6 +325,19 @@ def bkmeans(codes, sample, init, iters: int, bits: int | None = None, stream=Non
     out = torch.empty((i.size, bits // 64), dtype=torch.int64, device=codes.device)
     _check(lib().bdg_bkmeans(_ptr(codes), n, bits, s.ctypes.data, s.size, i.ctypes.data, i.size,
                              iters, _ptr(out), _stream(stream)))
+    return out
+
+
+def hamming_knn(queries, base, K: int, bits: int | None = None, stream=None):
+    """Exact Hamming kNN of ``queries`` against ``base`` (int64 ``[n][W]`` on the
+    GPU); returns ``(idx int32 [nq][K], dist int16 [nq][K])``."""
+    import torch
+    nq, words = queries.shape
+    bits = bits or 64 * words
+    out = (torch.empty((nq, K), dtype=torch.int32, device=queries.device),
+           torch.empty((nq, K), dtype=torch.int16, device=queries.device))
+    _check(lib().bdg_hamming_knn(_ptr(queries), nq, _ptr(base), base.shape[0], bits, K,
+                                 _ptr(out[0]), _ptr(out[1]), _stream(stream)))
     return out
 
 

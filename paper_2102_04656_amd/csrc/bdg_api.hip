@@ -50,6 +50,14 @@ constexpr uint32_t kMaxColBlock = 1u << 21;  // column index field of a tile key
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Sentinel rows (no neighbour): index BDG_NO_IDX, distance BDG_NO_DIST.
+__global__ void pad_rows_kernel(uint32_t* out_idx, uint16_t* out_dist, size_t cells) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= cells) return;
+  out_idx[i] = BDG_NO_IDX;
+  out_dist[i] = (uint16_t)BDG_NO_DIST;
+}
+
 // Test hook: BDG_TEST_FAIL_ALLOC=1 makes workspace allocations fail.
 bool forced_alloc_failure() {
   const char* s = getenv("BDG_TEST_FAIL_ALLOC");
@@ -534,6 +542,64 @@ int bdg_build_knn_dac(const uint64_t* codes, uint32_t n, uint32_t bits, const ui
   hipError_t f = hipFreeAsync(ws, st);
   if (e != hipSuccess) return device_error(e, "dac launch");
   if (f != hipSuccess) return device_error(f, "dac scratch");
+  return BDG_OK;
+}
+
+int bdg_hamming_knn(const uint64_t* queries, uint32_t nq, const uint64_t* base, uint32_t nb,
+                    uint32_t bits, uint32_t K, uint32_t* out_idx, uint16_t* out_dist,
+                    void* stream) {
+  g_last_error.clear();
+  if (bits == 0 || bits % 64 != 0)
+    return set_error(BDG_EINVAL, "bits must be a positive multiple of 64 (got %u)", bits);
+  if (bits > BDG_MAX_BITS) return set_error(BDG_EUNSUPPORTED, "bits > %u", BDG_MAX_BITS);
+  if (K == 0) return set_error(BDG_EINVAL, "K must be >= 1");
+  if (K > 64) return set_error(BDG_EUNSUPPORTED, "K > 64");
+  const uint32_t words = bits / 64;
+  if (nb > 0 && !bdg::run_supported(nb, words, K))
+    return set_error(BDG_EUNSUPPORTED, "nb=%u too large for %u-bit keys", nb, bits);
+  if (nq == 0) return BDG_OK;
+  if (!queries || !out_idx || !out_dist || (nb > 0 && !base))
+    return set_error(BDG_EINVAL, "null device pointer");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
+  if (nb == 0) {  // every row is padding
+    const size_t cells = (size_t)nq * K;
+    hipLaunchKernelGGL(pad_rows_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st,
+                       out_idx, out_dist, cells);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? BDG_OK : device_error(e, "hamming knn padding");
+  }
+  // the base's operand fragments
+  void* frags = nullptr;
+  hipError_t e = hipMallocAsync(&frags, bdg::prep_bytes(nb, words), st);
+  if (e != hipSuccess || !frags) {
+    (void)hipGetLastError();
+    return set_error(BDG_ENOMEM, "fragments of %u base rows", nb);
+  }
+  e = bdg::launch_prep(base, nb, words, frags, st);
+  if (e == hipSuccess) {
+    // rows = the queries, columns = the base: the rectangular tile, lists of
+    // (distance, base index), no row left out
+    bdg::RunArgs r;
+    r.codes = queries;
+    r.frags = frags;
+    r.words = words;
+    r.bits = bits;
+    r.K = K;
+    r.idx_bits = bdg::run_idx_bits(bits);
+    r.row0 = 0;
+    r.nrows = nq;
+    r.cb = 0;
+    r.ce = nb;
+    r.fresh = 1;
+    r.out_idx = out_idx;
+    r.out_dist = out_dist;
+    r.rect = 1;
+    e = bdg::launch_mfma_run(r, st);
+  }
+  hipError_t f = hipFreeAsync(frags, st);
+  if (e != hipSuccess) return device_error(e, "hamming knn launch");
+  if (f != hipSuccess) return device_error(f, "hamming knn scratch");
   return BDG_OK;
 }
 

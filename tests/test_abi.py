@@ -200,3 +200,17 @@ def test_bound_group_validation():
         assert "bound_group" in bdg.last_error()
     assert L.bdg_batch_plan_set_bound(None, 256) == bdg.BDG_EINVAL
     assert L.bdg_batch_plan_set_timing(None, None, None) == bdg.BDG_EINVAL
+
+
+def test_hamming_knn_validates_before_touching_the_gpu():
+    L = bdg.lib()
+    assert L.bdg_hamming_knn(FAKE, 10, FAKE, 20, 100, 4, FAKE, FAKE, None) == bdg.BDG_EINVAL
+    assert L.bdg_hamming_knn(FAKE, 10, FAKE, 20, 2048, 4, FAKE, FAKE, None) == bdg.BDG_EUNSUPPORTED
+    assert L.bdg_hamming_knn(FAKE, 10, FAKE, 20, 256, 0, FAKE, FAKE, None) == bdg.BDG_EINVAL
+    assert L.bdg_hamming_knn(FAKE, 10, FAKE, 20, 256, 65, FAKE, FAKE, None) == bdg.BDG_EUNSUPPORTED
+    # base rows beyond the key's index field at 512 bits (2^22 - 1 at most)
+    assert L.bdg_hamming_knn(FAKE, 10, FAKE, 1 << 22, 512, 8, FAKE, FAKE, None) == \
+        bdg.BDG_EUNSUPPORTED
+    assert L.bdg_hamming_knn(None, 10, FAKE, 20, 256, 4, FAKE, FAKE, None) == bdg.BDG_EINVAL
+    assert L.bdg_hamming_knn(FAKE, 10, None, 20, 256, 4, FAKE, FAKE, None) == bdg.BDG_EINVAL
+    assert L.bdg_hamming_knn(None, 0, None, 20, 256, 4, None, None, None) == bdg.BDG_OK

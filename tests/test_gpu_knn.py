@@ -404,3 +404,36 @@ def test_check_reports_a_wait_that_gave_up():
         if want == bdg.BDG_OK:
             assert_same(bdg.to_numpy_graph(idx, dist), oracle.knn_rows(codes, K),
                         f"col_block={col_block}")
+
+
+# ------------------------------------------- queries against a base set
+
+@pytest.mark.parametrize("nq,nb,bits,K", [
+    (1000, 3000, 256, 32), (777, 5001, 512, 64), (300, 40, 128, 50),  # nb < K: padding
+    (129, 1, 64, 8), (2048, 20000, 1024, 16), (65, 700, 192, 1),
+])
+def test_hamming_knn_against_a_base(nq, nb, bits, K):
+    g = np.random.default_rng(nq + nb)
+    base = datagen.clustered_codes(nb, bits, max(1, nb // 100), 0.2, seed=nq + bits)
+    # queries: fresh codes of the same clusters, and some rows of the base itself
+    queries = datagen.clustered_codes(nq, bits, max(1, nb // 100), 0.2, seed=nq + bits)
+    queries[::7] = base[g.integers(0, nb, queries[::7].shape[0])]
+    want = oracle.knn_rect(queries, base, K)
+    print(f"[hamming knn] nq={nq} nb={nb} bits={bits} K={K}", flush=True)
+    got = bdg.hamming_knn(dev(queries), dev(base), K)
+    import torch
+    torch.cuda.synchronize()
+    assert_same(bdg.to_numpy_graph(*got), want, f"nq={nq} nb={nb}")
+
+
+def test_hamming_knn_empty_base_and_ties():
+    import torch
+    queries = datagen.uniform_codes(70, 256, seed=3)
+    base = np.zeros((0, 4), dtype=np.uint64)
+    gi, gd = bdg.to_numpy_graph(*bdg.hamming_knn(dev(queries), dev(base), 5, bits=256))
+    assert (gi == 0xFFFFFFFF).all() and (gd == 0xFFFF).all()
+    # identical base codes: every distance equal, neighbours are the smallest indices
+    base = np.tile(datagen.uniform_codes(1, 256, seed=4), (500, 1))
+    got = bdg.hamming_knn(dev(queries), dev(base), 40)
+    torch.cuda.synchronize()
+    assert_same(bdg.to_numpy_graph(*got), oracle.knn_rect(queries, base, 40), "ties")

@@ -303,3 +303,31 @@ def test_unplanted_mutant_passes():
     """The harness itself: the copy without a planted mistake passes every pin."""
     ok = _mutant("none")
     assert all(pin(ok) for pin in PINS)
+
+
+def test_rect_knn_pins():
+    # queries against a separate base (no row left out): pinned to the plain
+    # per-bit definition and to the graph's definition on the same codes
+    g = np.random.default_rng(41)
+    base = datagen.clustered_codes(60, 128, 4, 0.2, seed=41)
+    queries = datagen.clustered_codes(9, 128, 4, 0.2, seed=42)
+    K = 7
+    oi, od = oracle.knn_rect(queries, base, K)
+    for q in range(queries.shape[0]):
+        # per-bit brute force with a full sort by (distance, index)
+        d = [sum(((int(queries[q, w]) ^ int(base[j, w])) >> b) & 1
+                 for w in range(2) for b in range(64)) for j in range(base.shape[0])]
+        want = sorted(range(base.shape[0]), key=lambda j: (d[j], j))[:K]
+        assert list(oi[q]) == want and list(od[q]) == [d[j] for j in want]
+    # queries = the base itself: each row finds itself first at distance 0,
+    # then exactly the graph's row (distinct codes)
+    codes = np.unique(datagen.uniform_codes(80, 64, seed=43), axis=0)
+    ri, rd = oracle.knn_rect(codes, codes, K + 1)
+    gi, gd = oracle.knn_rows(codes, K)
+    assert (ri[:, 0] == np.arange(codes.shape[0])).all() and (rd[:, 0] == 0).all()
+    assert np.array_equal(ri[:, 1:], gi) and np.array_equal(rd[:, 1:], gd)
+    # fewer base rows than K: padded; an empty base: all padding
+    pi, pd = oracle.knn_rect(queries, base[:3], 5)
+    assert (pi[:, 3:] == oracle.NO_IDX).all() and (pd[:, 3:] == oracle.NO_DIST).all()
+    ei, ed = oracle.knn_rect(queries, base[:0], 4)
+    assert (ei == oracle.NO_IDX).all() and (ed == oracle.NO_DIST).all()
