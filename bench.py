@@ -583,7 +583,7 @@ def measure_peaks():
 
 
 def time_build(w, workload, path, steps, warmup, other_steps, other_warmup, other_path,
-               autotune=False, bound_group=0):
+               autotune=False, bound_group=0, schedule=0):
     """Generate one single-partition workload, time its build on `path` (and
     the other distance path for `other_steps`), return (codes, codes_dev,
     outputs of the main path, result fields). With `autotune` the schedule
@@ -601,7 +601,18 @@ def time_build(w, workload, path, steps, warmup, other_steps, other_warmup, othe
     torch.cuda.synchronize()
 
     paths = {"mfma": bdg.PATH_MFMA, "popc": bdg.PATH_POPC}
-    schedule, tuned = 0, None
+    if schedule < 0:
+        # lists kept in global memory (eight compute waves) where built: the
+        # faster schedule for 256- and 512-bit codes with 65..128 keys
+        schedule = bdg.SCHEDULE_DEFAULT
+        if path == "mfma":
+            try:
+                bdg.bdg_build_knn_workspace_size(n, bits, K, bdg.make_opts(
+                    path=bdg.PATH_MFMA, tile_schedule=bdg.SCHEDULE_GLOBAL_LISTS))
+                schedule = bdg.SCHEDULE_GLOBAL_LISTS
+            except bdg.BdgError:
+                pass
+    tuned = None
     if autotune:
         log(f"[bench] {workload}: autotuning the build schedule")
         os.environ.setdefault("BDG_AUTOTUNE_LOG", "1")  # one stderr line per candidate
@@ -701,6 +712,11 @@ def main():
     ap.add_argument("--other-warmup", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--schedule", type=int, default=-1,
+                    help="tile schedule of the headline build (BDG_SCHEDULE_*; the graph is "
+                         "the same under each); -1: the global-lists schedule where the "
+                         "library builds it for the workload, else the default; --autotune "
+                         "overrides it")
     ap.add_argument("--bound-group", type=int, default=0,
                     help="admission bounds of the matrix-core build: rows per pivot group "
                          "(0: the library default, 1: off)")
@@ -740,7 +756,8 @@ def main():
     peaks = measure_peaks()
     codes, codes_dev, outs, res = time_build(w, args.workload, main_path, args.steps, args.warmup,
                                              args.other_steps, args.other_warmup, args.other_path,
-                                             autotune=args.autotune, bound_group=args.bound_group)
+                                             autotune=args.autotune, bound_group=args.bound_group,
+                                             schedule=args.schedule)
     n, bits, K = w["n"], w["bits"], w["K"]
     result = {
         "metric": METRIC,

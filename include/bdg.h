@@ -130,6 +130,12 @@ typedef struct bdg_knn_opts {
 #define BDG_SCHEDULE_DEFAULT 0   /* 32 pending keys per row */
 #define BDG_SCHEDULE_DEEP_RING 1 /* 16 pending keys per row, more stages in
                                     flight; codes of 128, 256 or 512 bits */
+#define BDG_SCHEDULE_GLOBAL_LISTS 2 /* single builds only: the rows' running
+                                    lists stay in the output index rows
+                                    between column blocks instead of LDS,
+                                    which leaves room for twice the compute
+                                    waves; codes of 256 or 512 bits with
+                                    65..128 keys */
 
 /* ---------------------------------------------------------------- build --- */
 

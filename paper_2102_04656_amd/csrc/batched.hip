@@ -234,7 +234,7 @@ int bdg_batch_plan_create(const uint64_t* offsets, uint32_t S, uint32_t bits, ui
   p->order = (opts && opts->tile_variant == BDG_ORDER_SHARD) ? BDG_ORDER_SHARD
                                                              : BDG_ORDER_LONGEST_FIRST;
   p->schedule = (opts && opts->struct_size >= sizeof(bdg_knn_opts)) ? (int)opts->tile_schedule : 0;
-  if (!bdg::schedule_supported(words, K, p->schedule)) {
+  if (!bdg::schedule_supported(words, K, p->schedule, true)) {
     const int sc = p->schedule;
     delete p;
     return bdg::api_error(BDG_EUNSUPPORTED, "tile schedule %d is not built for bits=%u", sc, bits);
@@ -350,7 +350,7 @@ int bdg_batch_plan_set_schedule(bdg_batch_plan* plan, int schedule) {
   if (!plan) return bdg::api_error(BDG_EINVAL, "plan is NULL");
   if (schedule < 0 || schedule >= bdg::kTileSchedules)
     return bdg::api_error(BDG_EINVAL, "unknown tile schedule %d", schedule);
-  if (!bdg::schedule_supported(plan->words, plan->K, schedule))
+  if (!bdg::schedule_supported(plan->words, plan->K, schedule, true))
     return bdg::api_error(BDG_EUNSUPPORTED, "tile schedule %d is not built for bits=%u", schedule,
                           plan->bits);
   if (schedule == plan->schedule) return BDG_OK;

@@ -93,10 +93,12 @@ struct RunArgs {
 uint32_t run_idx_bits(uint32_t bits);
 bool run_supported(uint32_t n, uint32_t words, uint32_t K);
 // Tile schedules of the persistent build and the batched launch (they differ
-// in pending-buffer size and stage-ring depth, never in the result): 0 always;
-// 1 for codes of 128, 256 or 512 bits.
-constexpr int kTileSchedules = 2;
-bool schedule_supported(uint32_t words, uint32_t K, int schedule);
+// in pending-buffer size, stage-ring depth and where the running lists live,
+// never in the result): 0 always; 1 for codes of 128, 256 or 512 bits; 2
+// (lists in global memory, more compute waves) for single builds of codes of
+// 256 or 512 bits with 65..128 keys.
+constexpr int kTileSchedules = 3;
+bool schedule_supported(uint32_t words, uint32_t K, int schedule, bool batched = false);
 uint32_t run_rows_per_wg(uint32_t K);
 // Operand prep: {0, 1} int8 fragments of every code, prep_bytes(n, words) bytes.
 size_t prep_bytes(uint32_t n, uint32_t words);

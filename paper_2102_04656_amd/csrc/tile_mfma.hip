@@ -87,9 +87,10 @@ bool run_supported(uint32_t n, uint32_t words, uint32_t K) {
   return mfma::run_lds_bytes(words, K) <= 160 * 1024;
 }
 
-bool schedule_supported(uint32_t words, uint32_t K, int schedule) {
+bool schedule_supported(uint32_t words, uint32_t K, int schedule, bool batched) {
   if (schedule == 0) return true;
   if (schedule == 1) return (words == 2 || words == 4 || words == 8) && K >= 1 && K <= 256;
+  if (schedule == 2) return !batched && (words == 4 || words == 8) && K > 64 && K <= 128;
   return false;
 }
 

@@ -181,6 +181,12 @@ def test_schedule_validation():
     assert call_ex(bits=192, opts=o) == bdg.BDG_EUNSUPPORTED
     o = bdg.make_opts(path=bdg.PATH_MFMA, tile_schedule=7)
     assert call_ex(bits=256, opts=o) == bdg.BDG_EUNSUPPORTED
+    # schedule 2 (lists in global memory): 256 or 512 bits, 65..128 keys
+    o = bdg.make_opts(path=bdg.PATH_MFMA, tile_schedule=bdg.SCHEDULE_GLOBAL_LISTS)
+    for bits, K in ((512, 64), (512, 129), (128, 100), (384, 100)):
+        assert call_ex(n=1000, bits=bits, K=K, opts=o) == bdg.BDG_EUNSUPPORTED, (bits, K)
+    for bits, K in ((512, 65), (256, 128)):
+        assert bdg.bdg_build_knn_workspace_size(1000, bits, K, o) > 0, (bits, K)
     assert L.bdg_batch_plan_set_schedule(None, 1) == bdg.BDG_EINVAL
 
 

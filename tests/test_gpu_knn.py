@@ -165,6 +165,56 @@ def test_admission_bounds_on_ties():
                     f"repeated K={K}")
 
 
+# ------------------------------------- lists in global memory (schedule 2)
+
+@pytest.mark.parametrize("n,bits,K,col_block", [
+    (3000, 512, 100, 0), (3000, 512, 100, 700), (2600, 256, 65, 1000), (1100, 512, 128, 300),
+    (257, 256, 128, 0),  # K near n: ragged last tile, padded rows
+    (129, 512, 127, 50),
+])
+def test_global_lists_schedule(n, bits, K, col_block):
+    # the running lists stay keys in the output rows between column blocks;
+    # the graph is the same as the oracle's, with and without admission bounds
+    codes = datagen.clustered_codes(n, bits, max(2, n // 150), 0.2, seed=n + K + bits)
+    want = oracle.knn_rows(codes, K)
+    for group in (bdg.BOUND_OFF, 64, bdg.BOUND_GROUP_DEFAULT):
+        print(f"[global lists] n={n} bits={bits} K={K} col_block={col_block} group={group}",
+              flush=True)
+        got = gpu_knn(codes, K, MFMA, schedule=bdg.SCHEDULE_GLOBAL_LISTS, col_block=col_block,
+                      bound_group=group)
+        assert_same(got, want, f"group={group}")
+
+
+def test_autotune_tries_global_lists():
+    # the build autotuner times schedule 2 where it is built; every candidate
+    # gives the oracle's graph
+    import json
+    codes = datagen.clustered_codes(4000, 512, 30, 0.2, seed=41)
+    want = oracle.knn_rows(codes, 100)
+    d = dev(codes)
+    opts, report = bdg.autotune_build(d, 100)
+    cands = json.loads(report)["candidates"]
+    assert bdg.SCHEDULE_GLOBAL_LISTS in {c["schedule"] for c in cands}
+    for c in cands:
+        print(f"[autotune] candidate {c}", flush=True)
+        got = bdg.to_numpy_graph(*bdg.build_knn(d, 100, path=c["path"], col_block=c["col_block"],
+                                                schedule=c["schedule"],
+                                                bound_group=c["bound_group"]))
+        assert_same(got, want, str(c))
+
+
+def test_global_lists_schedule_not_everywhere():
+    # built for 256 and 512 bits with 65..128 keys, single builds only
+    codes = dev(datagen.uniform_codes(300, 512, seed=3))
+    for bits, K in ((512, 64), (512, 129), (128, 100)):
+        c = codes if bits == 512 else dev(datagen.uniform_codes(300, bits, seed=3))
+        with pytest.raises(RuntimeError, match="schedule"):
+            bdg.build_knn(c, K, path=MFMA, schedule=bdg.SCHEDULE_GLOBAL_LISTS)
+    with pytest.raises(RuntimeError, match="schedule"):
+        bdg.BatchPlan(np.array([0, 300], dtype=np.uint64), 512, 100,
+                      schedule=bdg.SCHEDULE_GLOBAL_LISTS)
+
+
 # ------------------------------------------------- long lists (K > 256)
 
 @pytest.mark.parametrize("n,bits,K,col_block", [
