@@ -130,12 +130,12 @@ typedef struct bdg_knn_opts {
 #define BDG_SCHEDULE_DEFAULT 0   /* 32 pending keys per row */
 #define BDG_SCHEDULE_DEEP_RING 1 /* 16 pending keys per row, more stages in
                                     flight; codes of 128, 256 or 512 bits */
-#define BDG_SCHEDULE_GLOBAL_LISTS 2 /* single builds only: the rows' running
-                                    lists stay in the output index rows
-                                    between column blocks instead of LDS,
-                                    which leaves room for twice the compute
-                                    waves; codes of 256 or 512 bits with
-                                    65..128 keys */
+#define BDG_SCHEDULE_GLOBAL_LISTS 2 /* the rows' running lists are kept as
+                                    keys in the output index rows instead
+                                    of LDS, which leaves room for eight
+                                    compute waves of 48 rows (each operand
+                                    read feeds more products); codes of 128,
+                                    256 or 512 bits with up to 128 keys */
 
 /* ---------------------------------------------------------------- build --- */
 
@@ -377,7 +377,8 @@ int bdg_batch_plan_create(const uint64_t *offsets, uint32_t S, uint32_t bits, ui
                           const bdg_knn_opts *opts, bdg_batch_plan **plan);
 void bdg_batch_plan_destroy(bdg_batch_plan *plan);
 int bdg_batch_plan_info(const bdg_batch_plan *plan, bdg_batch_info *info);
-/* Change the tile schedule (BDG_SCHEDULE_*; drops a captured graph);
+/* Change the tile schedule (BDG_SCHEDULE_*; rebuilds the work items, whose
+ * rows follow the schedule's tile, and drops a captured graph);
  * BDG_EUNSUPPORTED if the schedule is not built for the plan's code length. */
 int bdg_batch_plan_set_schedule(bdg_batch_plan *plan, int schedule);
 /* Change the admission bounds (bound_group as in bdg_knn_opts: 0 = default,

@@ -34,6 +34,7 @@ void api_clear_error();
 struct bdg_batch_plan {
   uint32_t S = 0, bits = 0, words = 0, K = 0, idx_bits = 0;
   uint32_t n_total = 0, nitems = 0, grid = 0;
+  uint32_t item_cap = 0;          // items the device item buffer holds
   int order = BDG_ORDER_LONGEST_FIRST;
   int schedule = 0;               // tile schedule (BDG_SCHEDULE_*)
   std::vector<uint64_t> offsets;  // host copy, S + 1 entries
@@ -97,8 +98,11 @@ void drop_graph(bdg_batch_plan* p) {
 
 int upload_items(bdg_batch_plan* p) {
   std::vector<bdg::BatchItem> items =
-      make_items(p->offsets, bdg::run_rows_per_wg(p->K), p->order);
-  if (items.size() != p->nitems) return bdg::api_error(BDG_EDEVICE, "work item count changed");
+      make_items(p->offsets, bdg::sched_rows_per_wg(p->K, p->schedule), p->order);
+  // the item buffer holds the items of the smallest tile (every schedule's
+  // tile has at least run_rows_per_wg(K) rows)
+  if (items.size() > p->item_cap) return bdg::api_error(BDG_EDEVICE, "work item count changed");
+  p->nitems = (uint32_t)items.size();
   if (p->nitems) {
     // A launch of this plan may still be in flight on any stream (a pool
     // stream does not wait for the null stream): let every queued launch
@@ -234,12 +238,14 @@ int bdg_batch_plan_create(const uint64_t* offsets, uint32_t S, uint32_t bits, ui
   p->order = (opts && opts->tile_variant == BDG_ORDER_SHARD) ? BDG_ORDER_SHARD
                                                              : BDG_ORDER_LONGEST_FIRST;
   p->schedule = (opts && opts->struct_size >= sizeof(bdg_knn_opts)) ? (int)opts->tile_schedule : 0;
-  if (!bdg::schedule_supported(words, K, p->schedule, true)) {
+  if (!bdg::schedule_supported(words, K, p->schedule)) {
     const int sc = p->schedule;
     delete p;
     return bdg::api_error(BDG_EUNSUPPORTED, "tile schedule %d is not built for bits=%u", sc, bits);
   }
-  p->nitems = (uint32_t)make_items(p->offsets, bdg::run_rows_per_wg(K), p->order).size();
+  p->item_cap = (uint32_t)make_items(p->offsets, bdg::run_rows_per_wg(K), p->order).size();
+  p->nitems = (uint32_t)make_items(p->offsets, bdg::sched_rows_per_wg(K, p->schedule),
+                                   p->order).size();
   int dev = 0, cus = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -248,7 +254,7 @@ int bdg_batch_plan_create(const uint64_t* offsets, uint32_t S, uint32_t bits, ui
     return bdg::api_device_error(e, "device query");
   }
   p->grid = (uint32_t)(cus > 0 ? cus : 1);
-  const size_t items_bytes = align256((size_t)std::max<uint32_t>(p->nitems, 1) *
+  const size_t items_bytes = align256((size_t)std::max<uint32_t>(p->item_cap, 1) *
                                       sizeof(bdg::BatchItem));
   p->dev_bytes = items_bytes + 256 + align256(bdg::prep_bytes(p->n_total, words));
   // admission bounds: shards with more than K + 1 rows exist
@@ -350,7 +356,7 @@ int bdg_batch_plan_set_schedule(bdg_batch_plan* plan, int schedule) {
   if (!plan) return bdg::api_error(BDG_EINVAL, "plan is NULL");
   if (schedule < 0 || schedule >= bdg::kTileSchedules)
     return bdg::api_error(BDG_EINVAL, "unknown tile schedule %d", schedule);
-  if (!bdg::schedule_supported(plan->words, plan->K, schedule, true))
+  if (!bdg::schedule_supported(plan->words, plan->K, schedule))
     return bdg::api_error(BDG_EUNSUPPORTED, "tile schedule %d is not built for bits=%u", schedule,
                           plan->bits);
   if (schedule == plan->schedule) return BDG_OK;
@@ -358,8 +364,9 @@ int bdg_batch_plan_set_schedule(bdg_batch_plan* plan, int schedule) {
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return bdg::api_device_error(e, "synchronize");
   plan->schedule = schedule;
-  drop_graph(plan);  // the captured launch holds the old kernel
-  return BDG_OK;
+  // the tile's rows may differ: new work items (this drops the captured
+  // launch, which holds the old kernel)
+  return upload_items(plan);
 }
 
 int bdg_batch_plan_set_bound(bdg_batch_plan* plan, uint32_t bound_group) {

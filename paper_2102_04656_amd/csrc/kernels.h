@@ -95,10 +95,13 @@ bool run_supported(uint32_t n, uint32_t words, uint32_t K);
 // Tile schedules of the persistent build and the batched launch (they differ
 // in pending-buffer size, stage-ring depth and where the running lists live,
 // never in the result): 0 always; 1 for codes of 128, 256 or 512 bits; 2
-// (lists in global memory, more compute waves) for single builds of codes of
-// 256 or 512 bits with 65..128 keys.
+// (lists in global memory, more rows per compute wave) for codes of 128, 256
+// or 512 bits with up to 128 keys.
 constexpr int kTileSchedules = 3;
-bool schedule_supported(uint32_t words, uint32_t K, int schedule, bool batched = false);
+bool schedule_supported(uint32_t words, uint32_t K, int schedule);
+// Rows of one tile (work-group) of the persistent launches under a schedule;
+// never fewer than run_rows_per_wg(K).
+uint32_t sched_rows_per_wg(uint32_t K, int schedule);
 uint32_t run_rows_per_wg(uint32_t K);
 // Operand prep: {0, 1} int8 fragments of every code, prep_bytes(n, words) bytes.
 size_t prep_bytes(uint32_t n, uint32_t words);

@@ -87,10 +87,10 @@ bool run_supported(uint32_t n, uint32_t words, uint32_t K) {
   return mfma::run_lds_bytes(words, K) <= 160 * 1024;
 }
 
-bool schedule_supported(uint32_t words, uint32_t K, int schedule, bool batched) {
+bool schedule_supported(uint32_t words, uint32_t K, int schedule) {
   if (schedule == 0) return true;
   if (schedule == 1) return (words == 2 || words == 4 || words == 8) && K >= 1 && K <= 256;
-  if (schedule == 2) return !batched && (words == 4 || words == 8) && K > 64 && K <= 128;
+  if (schedule == 2) return (words == 2 || words == 4 || words == 8) && K >= 1 && K <= 128;
   return false;
 }
 
@@ -110,6 +110,10 @@ hipError_t launch_prep(const uint64_t* codes, uint32_t n, uint32_t words, void* 
 }
 
 uint32_t run_rows_per_wg(uint32_t K) { return (uint32_t)(mfma::nw_of(K) * 16 * mfma::qg_of(K)); }
+
+uint32_t sched_rows_per_wg(uint32_t K, int schedule) {
+  return schedule == 2 ? mfma::kGlRows : run_rows_per_wg(K);
+}
 
 hipError_t launch_mfma_batched(const BatchArgs& a, hipStream_t stream) {
   if (a.nitems == 0) return hipSuccess;

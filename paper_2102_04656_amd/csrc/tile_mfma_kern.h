@@ -745,11 +745,13 @@ __global__ __launch_bounds__(threads_of(W, NR), 1) void knn_mfma_run_kernel(
 }
 
 // Many independent partitions in one persistent launch: every work-group
-// takes work items (one shard's 4 QW rows against all the shard's columns)
+// takes work items (one shard's NW QW rows against all the shard's columns)
 // from a shared counter until the list is exhausted. Items are ordered
-// longest first, so the uneven shards balance over the CUs.
-template <int W, int NR, int QG, int GPS, int NST, int KB>
-__global__ __launch_bounds__(threads_of(W, NR), 1) void knn_mfma_batched_kernel(
+// longest first, so the uneven shards balance over the CUs. GL: the lists are
+// keys in the output index rows while the item runs (tile schedule 2).
+template <int W, int NR, int QG, int GPS, int NST, int KB, int NW = waves_of_nr(NR),
+          bool PR = use_producer(W, NR), bool GL = false>
+__global__ __launch_bounds__((NW + (PR ? 1 : 0)) * 64, 1) void knn_mfma_batched_kernel(
     const v4i* __restrict__ frags, const uint64_t* __restrict__ codes, uint32_t K, uint32_t bits,
     uint32_t IB, const BatchItem* __restrict__ items, uint32_t nitems, uint32_t* counter,
     uint32_t* __restrict__ out_idx, uint16_t* __restrict__ out_dist,
@@ -774,8 +776,10 @@ __global__ __launch_bounds__(threads_of(W, NR), 1) void knn_mfma_batched_kernel(
     job.out_idx = out_idx + (size_t)b.row0 * K;
     job.out_dist = out_dist + (size_t)b.row0 * K;
     job.bound = bound ? bound + (b.row0 - bound_base) : nullptr;
-    tile_body<W, NR, QG, GPS, NST, use_producer(W, NR), waves_of_nr(NR), KB>(
-        frags, codes, K, bits, IB, job, 0, ring, state);
+    job.keys = GL ? job.out_idx : nullptr;
+    job.last = 1;
+    tile_body<W, NR, QG, GPS, NST, PR, NW, KB, false, GL>(frags, codes, K, bits, IB, job, 0, ring,
+                                                          state);
   }
 }
 
@@ -962,29 +966,43 @@ inline hipError_t launch_sweep_w(const SweepArgs& a, hipStream_t stream) {
   return hipGetLastError();
 }
 
-// Tile schedule 2 (lists of 65..128 keys in global memory): eight compute
-// waves of 32 rows, two on each SIMD, no producer wave; the LDS holds the
-// pending buffers and a stage ring of kGlStages slots of 64 codes. (Measured
-// on 4M 512-bit codes, K = 100: 64-code stages beat 32-code ones, 3.9 %
-// faster than the LDS-resident lists of schedule 0 with three slots, while
-// deeper rings of smaller stages and 16-key pending buffers were slower.)
-constexpr int kGlStages = 3;
-constexpr bool gl_built(int W) { return W == 4 || W == 8; }
-constexpr size_t gl_state_bytes() { return state_bytes(0, 2, 8, 32); }
+// Tile schedule 2 (lists of up to 128 keys in global memory): eight compute
+// waves of 48 rows (three 16-row groups), two on each SIMD, so every candidate
+// operand read from the LDS feeds three products instead of two (at two groups
+// the eight waves' operand reads alone fill the LDS bandwidth). The LDS holds
+// the pending buffers (50 KB) and a stage ring of 64-code stages; where the
+// registers leave room (codes of up to 256 bits) a ninth wave produces the
+// stages, otherwise the compute waves copy them. Measured on 1M 256-bit codes,
+// K = 64, and 4M 512-bit codes, K = 100: 163.6 -> 136.9 ms and 5.16 -> 4.46 s
+// against schedule 0; two groups per wave: 197.6 ms and 4.97 s; four: spills
+// registers at 512 bits, 161.4 ms without a producer at 256.
+constexpr int kGlQG = 3, kGlWaves = 8, kGlGroups = 4;
+constexpr bool gl_built(int W) { return W == 2 || W == 4 || W == 8; }
+constexpr bool gl_producer(int W) { return W <= 4; }
+constexpr uint32_t kGlRows = kGlWaves * 16 * kGlQG;  // rows per tile
+constexpr size_t gl_state_bytes() { return state_bytes(0, kGlQG, kGlWaves, 32); }
+// Stage slots: three 32 KB stages without a producer (512 bits); with one, as
+// many as the LDS holds up to five (measured: 5 slots 136.9 ms, 3 slots 138.5
+// ms at 256 bits).
+constexpr int gl_stages(int W) {
+  if (!gl_producer(W)) return 3;
+  const size_t n = (160 * 1024 - gl_state_bytes() - 256) / ((size_t)kGlGroups * W * 1024);
+  return n > 5 ? 5 : (int)n;
+}
+constexpr int gl_threads(int W) { return (kGlWaves + (gl_producer(W) ? 1 : 0)) * 64; }
 
-template <int W>
+template <int W, int NR>
 inline hipError_t launch_sweep_gl(const SweepArgs& a, hipStream_t stream) {
-  constexpr int NR = 2, QG = 2, NW = 8;
-  constexpr int GPS = 4;
-  constexpr int NST = kGlStages;
-  static_assert(sizeof(TileRing<GPS * W * 64, NST>) + gl_state_bytes() <= 160 * 1024,
+  constexpr int QG = kGlQG, NW = kGlWaves, GPS = kGlGroups, NST = gl_stages(W);
+  constexpr bool PR = gl_producer(W);
+  static_assert(NST >= 2 && sizeof(TileRing<GPS * W * 64, NST>) + gl_state_bytes() <= 160 * 1024,
                 "stage ring and buffers fit the LDS");
-  auto kern = knn_mfma_sweep_kernel<W, NR, QG, GPS, NST, 32, NW, false, true>;
+  auto kern = knn_mfma_sweep_kernel<W, NR, QG, GPS, NST, 32, NW, PR, true>;
   const size_t lds = gl_state_bytes();
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  constexpr uint32_t rt = NW * 16 * QG;
+  constexpr uint32_t rt = kGlRows;
   const uint32_t ntiles = (a.nrows + rt - 1) / rt;
   const uint32_t ncb = (a.ncols + a.col_block - 1) / a.col_block;
   if ((uint64_t)ntiles * ncb > 0xFFFFFFFFull) return hipErrorInvalidValue;
@@ -993,10 +1011,28 @@ inline hipError_t launch_sweep_gl(const SweepArgs& a, hipStream_t stream) {
   hipLaunchKernelGGL(zero_words_kernel, dim3((words + 255) / 256), dim3(256), 0, stream, a.ctl,
                      words);
   const uint32_t grid = a.grid < nitems ? a.grid : nitems;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), lds, stream,
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(gl_threads(W)), lds, stream,
                      reinterpret_cast<const v4i*>(a.frags), a.codes, a.K, a.bits, a.idx_bits,
                      a.row0, a.nrows, a.ncols, a.col_block, ntiles, nitems, a.ctl, a.out_idx,
                      a.out_dist, a.spin_limit ? a.spin_limit : kSweepSpinLimit, a.bound);
+  return hipGetLastError();
+}
+
+// Schedule 2 for batched plans: the same tile; an item covers all of its
+// shard's columns, so its lists start empty and end in the output rows.
+template <int W, int NR>
+inline hipError_t launch_batched_gl(const BatchArgs& a, hipStream_t stream) {
+  constexpr int QG = kGlQG, NW = kGlWaves, GPS = kGlGroups, NST = gl_stages(W);
+  constexpr bool PR = gl_producer(W);
+  auto kern = knn_mfma_batched_kernel<W, NR, QG, GPS, NST, 32, NW, PR, true>;
+  const size_t lds = gl_state_bytes();
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, stream, a.counter);
+  hipLaunchKernelGGL(kern, dim3(a.grid), dim3(gl_threads(W)), lds, stream,
+                     reinterpret_cast<const v4i*>(a.frags), a.codes, a.K, a.bits, a.idx_bits,
+                     a.items, a.nitems, a.counter, a.out_idx, a.out_dist, a.bound, a.bound_base);
   return hipGetLastError();
 }
 
@@ -1014,8 +1050,10 @@ inline hipError_t launch_sweep_sc(const SweepArgs& a, hipStream_t stream) {
 template <int W>
 inline hipError_t launch_sweep_nr(const SweepArgs& a, hipStream_t stream) {
   if (a.schedule == 2) {
-    if constexpr (gl_built(W))
-      if (a.K > 64 && a.K <= 128) return launch_sweep_gl<W>(a, stream);
+    if constexpr (gl_built(W)) {
+      if (a.K >= 1 && a.K <= 64) return launch_sweep_gl<W, 1>(a, stream);
+      if (a.K > 64 && a.K <= 128) return launch_sweep_gl<W, 2>(a, stream);
+    }
     return hipErrorInvalidValue;
   }
   if (a.schedule == 1) {
@@ -1038,6 +1076,13 @@ inline hipError_t launch_batched_sc(const BatchArgs& a, hipStream_t stream) {
 
 template <int W>
 inline hipError_t launch_batched_nr(const BatchArgs& a, hipStream_t stream) {
+  if (a.schedule == 2) {
+    if constexpr (gl_built(W)) {
+      if (a.K >= 1 && a.K <= 64) return launch_batched_gl<W, 1>(a, stream);
+      if (a.K > 64 && a.K <= 128) return launch_batched_gl<W, 2>(a, stream);
+    }
+    return hipErrorInvalidValue;
+  }
   if (a.schedule == 1) {
     if constexpr (sched_built(W, 1)) return launch_batched_sc<W, 1>(a, stream);
     return hipErrorInvalidValue;

@@ -181,11 +181,11 @@ def test_schedule_validation():
     assert call_ex(bits=192, opts=o) == bdg.BDG_EUNSUPPORTED
     o = bdg.make_opts(path=bdg.PATH_MFMA, tile_schedule=7)
     assert call_ex(bits=256, opts=o) == bdg.BDG_EUNSUPPORTED
-    # schedule 2 (lists in global memory): 256 or 512 bits, 65..128 keys
+    # schedule 2 (lists in global memory): 128, 256 or 512 bits, up to 128 keys
     o = bdg.make_opts(path=bdg.PATH_MFMA, tile_schedule=bdg.SCHEDULE_GLOBAL_LISTS)
-    for bits, K in ((512, 64), (512, 129), (128, 100), (384, 100)):
+    for bits, K in ((512, 129), (192, 100), (384, 100), (256, 200), (64, 8)):
         assert call_ex(n=1000, bits=bits, K=K, opts=o) == bdg.BDG_EUNSUPPORTED, (bits, K)
-    for bits, K in ((512, 65), (256, 128)):
+    for bits, K in ((512, 65), (256, 128), (256, 1), (512, 64), (128, 100)):
         assert bdg.bdg_build_knn_workspace_size(1000, bits, K, o) > 0, (bits, K)
     assert L.bdg_batch_plan_set_schedule(None, 1) == bdg.BDG_EINVAL
 

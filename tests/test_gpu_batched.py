@@ -58,12 +58,17 @@ def check_shard(gi, gd, codes, offsets, s, K, rows=None):
                              f"want {list(zip(want[1][r][:8], want[0][r][:8]))}")
 
 
-@pytest.mark.parametrize("bits,K", [(256, 32), (128, 7), (512, 100), (192, 64)])
-def test_small_and_ragged_shards(bits, K):
-    # empty, single-row, fewer rows than K, tile edges (255/256/257), and larger shards
-    sizes = [0, 1, 2, 17, 255, 256, 257, 600, 1000, 0, 3001, 40, 5]
+@pytest.mark.parametrize("bits,K,schedule", [
+    (256, 32, 0), (128, 7, 0), (512, 100, 0), (192, 64, 0),
+    (256, 32, 2), (128, 7, 2), (512, 100, 2), (512, 128, 2),  # lists in global memory
+])
+def test_small_and_ragged_shards(bits, K, schedule):
+    # empty, single-row, fewer rows than K, tile edges (255/256/257, 383/384/385),
+    # and larger shards
+    sizes = [0, 1, 2, 17, 255, 256, 257, 600, 1000, 0, 3001, 40, 5, 383, 384, 385]
     codes, offsets = shard_codes(sizes, bits, seed=bits + K)
-    plan = bdg.BatchPlan(offsets, bits, K)
+    print(f"[ragged shards] bits={bits} K={K} schedule={schedule}", flush=True)
+    plan = bdg.BatchPlan(offsets, bits, K, schedule=schedule)
     info = plan.info()
     assert info.shards == len(sizes) and info.rows == int(offsets[-1])
     out = plan.build(dev(codes))
@@ -125,6 +130,22 @@ def test_orders_graph_replay_and_autotune_agree():
     stream.synchronize()
     got = to_np(out)
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+    # lists in global memory: tiles of 384 rows, so fewer work items; the same
+    # graph eagerly and through a graph, and back
+    items = plan.info().work_items
+    plan.set_schedule(bdg.SCHEDULE_GLOBAL_LISTS)
+    assert plan.info().work_items == int(np.ceil(sizes / 384).sum()) < items
+    got = to_np(plan.build(d))
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+    for rep in range(2):
+        out[0].zero_()
+        torch.cuda.synchronize()
+        plan.build(d, out=out, stream=stream, graph=True)
+        stream.synchronize()
+        got = to_np(out)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), f"replay {rep}"
+    plan.set_schedule(bdg.SCHEDULE_DEEP_RING)
+    assert plan.info().work_items == items
     # admission bounds off, and other pivot-group sizes: the same graph
     for group in (bdg.BOUND_OFF, 16, 1024, bdg.BOUND_GROUP_DEFAULT):
         plan.set_bound(group)
@@ -143,8 +164,8 @@ def test_orders_graph_replay_and_autotune_agree():
     rep = json.loads(report)
     assert rep["knobs"] == ["order", "schedule", "bound_group"]
     cands = rep["candidates"]
-    assert len(cands) == 7  # 2 orders, then the other schedule, then 4 more bound settings
-    assert {c["order"] for c in cands} == {0, 1} and {c["schedule"] for c in cands} == {0, 1}
+    assert len(cands) == 8  # 2 orders, then the other 2 schedules, then 4 more bound settings
+    assert {c["order"] for c in cands} == {0, 1} and {c["schedule"] for c in cands} == {0, 1, 2}
     assert {256, bdg.BOUND_OFF, 128, 512, 64} == {c["bound_group"] for c in cands}
     got = to_np(plan.build(d))
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])

@@ -171,6 +171,8 @@ def test_admission_bounds_on_ties():
     (3000, 512, 100, 0), (3000, 512, 100, 700), (2600, 256, 65, 1000), (1100, 512, 128, 300),
     (257, 256, 128, 0),  # K near n: ragged last tile, padded rows
     (129, 512, 127, 50),
+    (2000, 256, 64, 500), (1500, 512, 16, 0), (40, 256, 1, 0), (5, 512, 8, 0),
+    (2300, 128, 100, 600), (385, 128, 32, 0),  # 128 bits; one row past a 384-row tile
 ])
 def test_global_lists_schedule(n, bits, K, col_block):
     # the running lists stay keys in the output rows between column blocks;
@@ -204,14 +206,14 @@ def test_autotune_tries_global_lists():
 
 
 def test_global_lists_schedule_not_everywhere():
-    # built for 256 and 512 bits with 65..128 keys, single builds only
+    # built for 128, 256 and 512 bits with up to 128 keys
     codes = dev(datagen.uniform_codes(300, 512, seed=3))
-    for bits, K in ((512, 64), (512, 129), (128, 100)):
+    for bits, K in ((512, 129), (192, 100), (384, 60)):
         c = codes if bits == 512 else dev(datagen.uniform_codes(300, bits, seed=3))
         with pytest.raises(RuntimeError, match="schedule"):
             bdg.build_knn(c, K, path=MFMA, schedule=bdg.SCHEDULE_GLOBAL_LISTS)
     with pytest.raises(RuntimeError, match="schedule"):
-        bdg.BatchPlan(np.array([0, 300], dtype=np.uint64), 512, 100,
+        bdg.BatchPlan(np.array([0, 300], dtype=np.uint64), 384, 100,
                       schedule=bdg.SCHEDULE_GLOBAL_LISTS)
 
 
