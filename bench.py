@@ -470,7 +470,14 @@ def bench_batched(args, w):
     log(f"[bench] generated {int(offsets[-1])} rows in {time.perf_counter() - t0:.1f}s; "
         f"{pairs:.4g} pairs")
     d = torch.from_numpy(codes.view(np.int64)).cuda()
-    plan = bdg.BatchPlan(offsets, bits, K, bound_group=args.bound_group)
+    # tile schedule: as asked, else lists in global memory where built
+    sched = args.schedule if args.schedule >= 0 else bdg.SCHEDULE_GLOBAL_LISTS
+    try:
+        plan = bdg.BatchPlan(offsets, bits, K, bound_group=args.bound_group, schedule=sched)
+    except bdg.BdgError:
+        if args.schedule >= 0:
+            raise
+        plan = bdg.BatchPlan(offsets, bits, K, bound_group=args.bound_group)
     out = plan.outputs()
     stream = torch.cuda.Stream()
     report = None
@@ -806,7 +813,7 @@ def main():
         w2 = datagen.WORKLOADS[args.secondary]
         _, _, o2, r2 = time_build(w2, args.secondary, "mfma", args.steps, args.warmup, 0, 0,
                                   other_path=False, autotune=args.autotune,
-                                  bound_group=args.bound_group)
+                                  bound_group=args.bound_group, schedule=args.schedule)
         del o2
         result["secondary"] = r2
     if args.recall:
