@@ -189,14 +189,19 @@ __global__ __launch_bounds__(256) void gather_pivots_kernel(const uint64_t* __re
 }
 
 // The three nearest pivots from the tile's three-element lists ((distance,
-// pivot) order; missing entries when there are fewer pivots).
+// pivot) order; missing entries when there are fewer pivots). Every entry
+// becomes an index below, so anything outside [0, npiv) is taken as missing
+// (a first entry as pivot 0): a bound from any group of other rows is still an
+// upper bound on the K-th distance, only a looser one.
 __global__ __launch_bounds__(256) void top3_kernel(BK a, const uint32_t* __restrict__ top) {
   const uint32_t i = blockIdx.x * 256 + threadIdx.x;
   if (i >= a.total) return;
-  const uint32_t g = top[3 * (size_t)i], g2 = top[3 * (size_t)i + 1], g3 = top[3 * (size_t)i + 2];
+  uint32_t g = top[3 * (size_t)i];
+  const uint32_t g2 = top[3 * (size_t)i + 1], g3 = top[3 * (size_t)i + 2];
+  if (g >= a.npiv) g = 0;
   a.nearest[i] = g;
-  a.second[i] = g2 == 0xFFFFFFFFu ? g : g2;
-  a.third[i] = g3 == 0xFFFFFFFFu ? g : g3;
+  a.second[i] = g2 >= a.npiv ? g : g2;
+  a.third[i] = g3 >= a.npiv ? g : g3;
   atomicAdd(&a.offs[g + 1], 1u);
 }
 
