@@ -470,14 +470,7 @@ def bench_batched(args, w):
     log(f"[bench] generated {int(offsets[-1])} rows in {time.perf_counter() - t0:.1f}s; "
         f"{pairs:.4g} pairs")
     d = torch.from_numpy(codes.view(np.int64)).cuda()
-    # tile schedule: as asked, else lists in global memory where built
-    sched = args.schedule if args.schedule >= 0 else bdg.SCHEDULE_GLOBAL_LISTS
-    try:
-        plan = bdg.BatchPlan(offsets, bits, K, bound_group=args.bound_group, schedule=sched)
-    except bdg.BdgError:
-        if args.schedule >= 0:
-            raise
-        plan = bdg.BatchPlan(offsets, bits, K, bound_group=args.bound_group)
+    plan = bdg.BatchPlan(offsets, bits, K, bound_group=args.bound_group, schedule=args.schedule)
     out = plan.outputs()
     stream = torch.cuda.Stream()
     report = None
@@ -589,6 +582,20 @@ def measure_peaks():
     return dict(MEASURED_PEAKS)
 
 
+def resolved_schedule(schedule, bits, K):
+    """The BDG_SCHEDULE_* value a build runs under: DEFAULT resolves to the
+    global-lists schedule where the library builds it, else the LDS lists."""
+    from paper_2102_04656_amd import bdg
+    if schedule != bdg.SCHEDULE_DEFAULT:
+        return schedule
+    try:
+        bdg.bdg_build_knn_workspace_size(1000, bits, K, bdg.make_opts(
+            path=bdg.PATH_MFMA, tile_schedule=bdg.SCHEDULE_GLOBAL_LISTS))
+        return bdg.SCHEDULE_GLOBAL_LISTS
+    except bdg.BdgError:
+        return bdg.SCHEDULE_LDS_LISTS
+
+
 def time_build(w, workload, path, steps, warmup, other_steps, other_warmup, other_path,
                autotune=False, bound_group=0, schedule=0):
     """Generate one single-partition workload, time its build on `path` (and
@@ -608,17 +615,6 @@ def time_build(w, workload, path, steps, warmup, other_steps, other_warmup, othe
     torch.cuda.synchronize()
 
     paths = {"mfma": bdg.PATH_MFMA, "popc": bdg.PATH_POPC}
-    if schedule < 0:
-        # lists kept in global memory (eight compute waves) where built: the
-        # faster schedule for 256- and 512-bit codes with 65..128 keys
-        schedule = bdg.SCHEDULE_DEFAULT
-        if path == "mfma":
-            try:
-                bdg.bdg_build_knn_workspace_size(n, bits, K, bdg.make_opts(
-                    path=bdg.PATH_MFMA, tile_schedule=bdg.SCHEDULE_GLOBAL_LISTS))
-                schedule = bdg.SCHEDULE_GLOBAL_LISTS
-            except bdg.BdgError:
-                pass
     tuned = None
     if autotune:
         log(f"[bench] {workload}: autotuning the build schedule")
@@ -681,7 +677,8 @@ def time_build(w, workload, path, steps, warmup, other_steps, other_warmup, othe
            "dtype": "i8" if path == "mfma" else "u32",
            "config": {"workload": workload, "n": n, "bits": bits, "K": K,
                       "row_block": row_block, "col_block": col_block, "path": path,
-                      "tile_schedule": schedule,
+                      "tile_schedule": resolved_schedule(schedule, bits, K) if path == "mfma"
+                      else None,
                       "bound_group": bound_group or bdg.BOUND_GROUP_DEFAULT,
                       "centres": w["n_centres"], "flip_p": w["p"], "seed": w["seed"]},
            "roofline": roof(path), "stall": runs[path]["kernel"]["stall"]}
@@ -719,11 +716,9 @@ def main():
     ap.add_argument("--other-warmup", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--schedule", type=int, default=-1,
-                    help="tile schedule of the headline build (BDG_SCHEDULE_*; the graph is "
-                         "the same under each); -1: the global-lists schedule where the "
-                         "library builds it for the workload, else the default; --autotune "
-                         "overrides it")
+    ap.add_argument("--schedule", type=int, default=0,
+                    help="tile schedule of the builds (BDG_SCHEDULE_*; the graph is the same "
+                         "under each); 0: the library's default; --autotune overrides it")
     ap.add_argument("--bound-group", type=int, default=0,
                     help="admission bounds of the matrix-core build: rows per pivot group "
                          "(0: the library default, 1: off)")

@@ -96,8 +96,8 @@ typedef struct bdg_knn_opts {
                                 is a test hook for the give-up path */
     uint32_t tile_schedule;  /* matrix-core tile schedule (BDG_SCHEDULE_*; the
                                 graph is the same under every schedule);
-                                default 0, or the autotuned one with path AUTO
-                                and col_block 0 */
+                                default 0 (the library's choice), or the
+                                autotuned one with path AUTO and col_block 0 */
     uint32_t bound_group;    /* matrix-core path: admission bounds before the
                                 search (BDG_BOUND_*): 0 = default (on, pivot
                                 groups of BDG_BOUND_GROUP_DEFAULT rows, or the
@@ -125,17 +125,23 @@ typedef struct bdg_knn_opts {
 #define BDG_BOUND_GROUP_MAX (1u << 24)
 
 /* Tile schedules of the matrix-core build and of batched plans. They differ
- * in the LDS split between the rows' pending-key buffers and the stage ring
- * of candidate operands, never in the result. */
-#define BDG_SCHEDULE_DEFAULT 0   /* 32 pending keys per row */
-#define BDG_SCHEDULE_DEEP_RING 1 /* 16 pending keys per row, more stages in
-                                    flight; codes of 128, 256 or 512 bits */
+ * in where the rows' running lists live, the size of their pending-key
+ * buffers and the depth of the stage ring of candidate operands, never in the
+ * result. */
+#define BDG_SCHEDULE_DEFAULT 0   /* the library's choice: GLOBAL_LISTS where it
+                                    is built for the code length and K (the
+                                    fastest measured there), else LDS_LISTS */
+#define BDG_SCHEDULE_DEEP_RING 1 /* lists in LDS, 16 pending keys per row,
+                                    more stages in flight; codes of 128, 256
+                                    or 512 bits */
 #define BDG_SCHEDULE_GLOBAL_LISTS 2 /* the rows' running lists are kept as
                                     keys in the output index rows instead
                                     of LDS, which leaves room for eight
                                     compute waves of 48 rows (each operand
                                     read feeds more products); codes of 128,
                                     256 or 512 bits with up to 128 keys */
+#define BDG_SCHEDULE_LDS_LISTS 3 /* lists in LDS, 32 pending keys per row;
+                                    every code length and K */
 
 /* ---------------------------------------------------------------- build --- */
 
@@ -358,7 +364,8 @@ typedef struct bdg_batch_plan bdg_batch_plan;
 typedef struct bdg_batch_info {
     uint32_t shards, rows, work_items, workgroups;
     int32_t order;         /* BDG_ORDER_* */
-    int32_t schedule;      /* BDG_SCHEDULE_* */
+    int32_t schedule;      /* BDG_SCHEDULE_* in force (never DEFAULT: the
+                              value it resolved to) */
     uint32_t bound_group;  /* rows per pivot group of the admission bounds, or
                               BDG_BOUND_OFF */
     uint32_t reserved;
@@ -377,8 +384,9 @@ int bdg_batch_plan_create(const uint64_t *offsets, uint32_t S, uint32_t bits, ui
                           const bdg_knn_opts *opts, bdg_batch_plan **plan);
 void bdg_batch_plan_destroy(bdg_batch_plan *plan);
 int bdg_batch_plan_info(const bdg_batch_plan *plan, bdg_batch_info *info);
-/* Change the tile schedule (BDG_SCHEDULE_*; rebuilds the work items, whose
- * rows follow the schedule's tile, and drops a captured graph);
+/* Change the tile schedule (BDG_SCHEDULE_*, DEFAULT resolved as for a build;
+ * rebuilds the work items, whose rows follow the schedule's tile, and drops a
+ * captured graph);
  * BDG_EUNSUPPORTED if the schedule is not built for the plan's code length. */
 int bdg_batch_plan_set_schedule(bdg_batch_plan *plan, int schedule);
 /* Change the admission bounds (bound_group as in bdg_knn_opts: 0 = default,

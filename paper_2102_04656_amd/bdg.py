@@ -73,7 +73,7 @@ class BatchInfo(ctypes.Structure):
 
 
 ORDER_LONGEST_FIRST, ORDER_SHARD = 0, 1
-SCHEDULE_DEFAULT, SCHEDULE_DEEP_RING, SCHEDULE_GLOBAL_LISTS = 0, 1, 2
+SCHEDULE_DEFAULT, SCHEDULE_DEEP_RING, SCHEDULE_GLOBAL_LISTS, SCHEDULE_LDS_LISTS = 0, 1, 2, 3
 BOUND_OFF, BOUND_GROUP_DEFAULT, BOUND_GROUP_MIN, BOUND_GROUP_MAX = 1, 256, 16, 1 << 24
 
 

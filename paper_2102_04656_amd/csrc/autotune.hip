@@ -205,7 +205,9 @@ int bdg_autotune_build(const uint64_t* codes, uint32_t n, uint32_t bits, uint32_
     }
     return (long)ok.size() - 1;
   };
-  Cand best{BDG_PATH_MFMA, 262144u, 0, BDG_BOUND_GROUP_DEFAULT, 0.f};
+  // the default schedule as the value it resolves to, so it is timed once
+  Cand best{BDG_PATH_MFMA, 262144u, bdg::resolve_schedule(bits / 64, K, 0),
+            BDG_BOUND_GROUP_DEFAULT, 0.f};
   long bi = -1;
   int st = BDG_OK;
   auto sweep = [&](std::vector<Cand> cs) {
@@ -222,12 +224,13 @@ int bdg_autotune_build(const uint64_t* codes, uint32_t n, uint32_t bits, uint32_
   };
   {
     std::vector<Cand> cs;
-    for (uint32_t cb : {262144u, 131072u, 524288u}) cs.push_back({BDG_PATH_MFMA, cb, 0, best.bound_group, 0.f});
+    for (uint32_t cb : {262144u, 131072u, 524288u})
+      cs.push_back({BDG_PATH_MFMA, cb, best.schedule, best.bound_group, 0.f});
     sweep(cs);
   }
   {
     std::vector<Cand> cs;
-    for (int sc = 0; sc < bdg::kTileSchedules; ++sc) {
+    for (int sc : bdg::kExplicitSchedules) {
       Cand c = best;
       c.schedule = sc;
       cs.push_back(c);
@@ -329,7 +332,12 @@ int bdg_autotune_batched(bdg_batch_plan* plan, const uint64_t* codes, uint32_t* 
   };
   {
     bdg_batch_info in;
+    // the library's default schedule, as the value it resolves to for this
+    // plan (so that it is timed once)
+    st = bdg_batch_plan_set_schedule(plan, BDG_SCHEDULE_DEFAULT);
+    if (st != BDG_OK) return st;
     bdg_batch_plan_info(plan, &in);
+    cur.schedule = in.schedule;
     if (in.bound_group == BDG_BOUND_OFF) {
       // no bounds unless the plan can take them
       if (bdg_batch_plan_set_bound(plan, BDG_BOUND_GROUP_DEFAULT) == BDG_OK) {
@@ -342,7 +350,7 @@ int bdg_autotune_batched(bdg_batch_plan* plan, const uint64_t* codes, uint32_t* 
          {BDG_ORDER_SHARD, cur.schedule, cur.bound_group, 0.f}});
   {
     std::vector<Cand> cs;
-    for (int sc = 0; sc < bdg::kTileSchedules; ++sc) cs.push_back({cur.order, sc, cur.bound_group, 0.f});
+    for (int sc : bdg::kExplicitSchedules) cs.push_back({cur.order, sc, cur.bound_group, 0.f});
     sweep(cs);
   }
   {

@@ -237,12 +237,12 @@ int bdg_batch_plan_create(const uint64_t* offsets, uint32_t S, uint32_t bits, ui
   p->offsets.assign(offsets, offsets + S + 1);
   p->order = (opts && opts->tile_variant == BDG_ORDER_SHARD) ? BDG_ORDER_SHARD
                                                              : BDG_ORDER_LONGEST_FIRST;
-  p->schedule = (opts && opts->struct_size >= sizeof(bdg_knn_opts)) ? (int)opts->tile_schedule : 0;
-  if (!bdg::schedule_supported(words, K, p->schedule)) {
-    const int sc = p->schedule;
+  const int sc = (opts && opts->struct_size >= sizeof(bdg_knn_opts)) ? (int)opts->tile_schedule : 0;
+  if (!bdg::schedule_supported(words, K, sc)) {
     delete p;
     return bdg::api_error(BDG_EUNSUPPORTED, "tile schedule %d is not built for bits=%u", sc, bits);
   }
+  p->schedule = bdg::resolve_schedule(words, K, sc);
   p->item_cap = (uint32_t)make_items(p->offsets, bdg::run_rows_per_wg(K), p->order).size();
   p->nitems = (uint32_t)make_items(p->offsets, bdg::sched_rows_per_wg(K, p->schedule),
                                    p->order).size();
@@ -359,6 +359,7 @@ int bdg_batch_plan_set_schedule(bdg_batch_plan* plan, int schedule) {
   if (!bdg::schedule_supported(plan->words, plan->K, schedule))
     return bdg::api_error(BDG_EUNSUPPORTED, "tile schedule %d is not built for bits=%u", schedule,
                           plan->bits);
+  schedule = bdg::resolve_schedule(plan->words, plan->K, schedule);
   if (schedule == plan->schedule) return BDG_OK;
   // a launch of the captured graph may still be queued: let it finish first
   hipError_t e = hipDeviceSynchronize();

@@ -127,7 +127,7 @@ int make_plan(uint32_t n, uint32_t bits, uint32_t K, const bdg_knn_opts* opts, P
   p->path = path;
   if (path == BDG_PATH_MFMA && !bdg::schedule_supported(p->words, K, schedule))
     return set_error(BDG_EUNSUPPORTED, "tile schedule %d is not built for bits=%u", schedule, bits);
-  p->schedule = path == BDG_PATH_MFMA ? schedule : 0;
+  p->schedule = path == BDG_PATH_MFMA ? bdg::resolve_schedule(p->words, K, schedule) : 0;
   uint32_t cb = (opts && opts->col_block)
                     ? opts->col_block
                     : (tuned_cb ? tuned_cb

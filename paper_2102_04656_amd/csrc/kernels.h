@@ -92,13 +92,19 @@ struct RunArgs {
 
 uint32_t run_idx_bits(uint32_t bits);
 bool run_supported(uint32_t n, uint32_t words, uint32_t K);
-// Tile schedules of the persistent build and the batched launch (they differ
-// in pending-buffer size, stage-ring depth and where the running lists live,
-// never in the result): 0 always; 1 for codes of 128, 256 or 512 bits; 2
-// (lists in global memory, more rows per compute wave) for codes of 128, 256
-// or 512 bits with up to 128 keys.
-constexpr int kTileSchedules = 3;
+// Tile schedules of the persistent build and the batched launch, numbered as
+// the API's BDG_SCHEDULE_* (they differ in pending-buffer size, stage-ring
+// depth and where the running lists live, never in the result): 3 (lists in
+// LDS) always; 1 (16-key buffers, deeper ring) for codes of 128, 256 or 512
+// bits; 2 (lists in global memory, more rows per compute wave) for codes of
+// 128, 256 or 512 bits with up to 128 keys. 0 is the default, resolved by
+// resolve_schedule before anything is launched.
+constexpr int kScheduleLds = 3;
+constexpr int kTileSchedules = 4;  // values 0 .. kTileSchedules - 1
+constexpr int kExplicitSchedules[] = {kScheduleLds, 1, 2};  // what a tuner sweeps
 bool schedule_supported(uint32_t words, uint32_t K, int schedule);
+// 0 -> 2 where built for (words, K), else 3; any other value unchanged.
+int resolve_schedule(uint32_t words, uint32_t K, int schedule);
 // Rows of one tile (work-group) of the persistent launches under a schedule;
 // never fewer than run_rows_per_wg(K).
 uint32_t sched_rows_per_wg(uint32_t K, int schedule);
@@ -125,7 +131,7 @@ struct BatchArgs {
   uint32_t grid;           // persistent work-groups
   uint32_t* out_idx;
   uint16_t* out_dist;
-  int schedule = 0;        // tile schedule (schedule_supported)
+  int schedule = kScheduleLds;  // tile schedule (resolved; schedule_supported)
   // Admission bounds (launch_bounds_pass) of the rows [bound_base, ...), or
   // nullptr: while a row's list is not full, only candidates at a distance of
   // at most its bound are admitted.
@@ -151,7 +157,7 @@ struct SweepArgs {
   uint32_t* out_idx;
   uint16_t* out_dist;
   uint32_t spin_limit = 0;  // polls of one dependency wait before it gives up (0: default)
-  int schedule = 0;         // tile schedule (schedule_supported)
+  int schedule = kScheduleLds;  // tile schedule (resolved; schedule_supported)
   const uint16_t* bound = nullptr;  // admission bounds of rows [0, ...), or nullptr
 };
 constexpr uint32_t kSweepStallWord = 1;  // ctl[1] != 0: a dependency wait ran out

@@ -88,10 +88,15 @@ bool run_supported(uint32_t n, uint32_t words, uint32_t K) {
 }
 
 bool schedule_supported(uint32_t words, uint32_t K, int schedule) {
-  if (schedule == 0) return true;
+  if (schedule == 0 || schedule == kScheduleLds) return true;
   if (schedule == 1) return (words == 2 || words == 4 || words == 8) && K >= 1 && K <= 256;
   if (schedule == 2) return (words == 2 || words == 4 || words == 8) && K >= 1 && K <= 128;
   return false;
+}
+
+int resolve_schedule(uint32_t words, uint32_t K, int schedule) {
+  if (schedule != 0) return schedule;
+  return schedule_supported(words, K, 2) ? 2 : kScheduleLds;
 }
 
 size_t prep_rows(uint32_t n) {

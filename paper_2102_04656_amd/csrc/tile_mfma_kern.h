@@ -1060,7 +1060,7 @@ inline hipError_t launch_sweep_nr(const SweepArgs& a, hipStream_t stream) {
     if constexpr (sched_built(W, 1)) return launch_sweep_sc<W, 1>(a, stream);
     return hipErrorInvalidValue;
   }
-  return a.schedule == 0 ? launch_sweep_sc<W, 0>(a, stream) : hipErrorInvalidValue;
+  return a.schedule == kScheduleLds ? launch_sweep_sc<W, 0>(a, stream) : hipErrorInvalidValue;
 }
 
 template <int W, int SC>
@@ -1087,7 +1087,7 @@ inline hipError_t launch_batched_nr(const BatchArgs& a, hipStream_t stream) {
     if constexpr (sched_built(W, 1)) return launch_batched_sc<W, 1>(a, stream);
     return hipErrorInvalidValue;
   }
-  return a.schedule == 0 ? launch_batched_sc<W, 0>(a, stream) : hipErrorInvalidValue;
+  return a.schedule == kScheduleLds ? launch_batched_sc<W, 0>(a, stream) : hipErrorInvalidValue;
 }
 
 template <int W>

@@ -187,6 +187,10 @@ def test_schedule_validation():
         assert call_ex(n=1000, bits=bits, K=K, opts=o) == bdg.BDG_EUNSUPPORTED, (bits, K)
     for bits, K in ((512, 65), (256, 128), (256, 1), (512, 64), (128, 100)):
         assert bdg.bdg_build_knn_workspace_size(1000, bits, K, o) > 0, (bits, K)
+    # schedule 3 (lists in LDS) and the default are built for every code length
+    for sc in (bdg.SCHEDULE_LDS_LISTS, bdg.SCHEDULE_DEFAULT):
+        o = bdg.make_opts(path=bdg.PATH_MFMA, tile_schedule=sc)
+        assert bdg.bdg_build_knn_workspace_size(1000, 192, 200, o) > 0
     assert L.bdg_batch_plan_set_schedule(None, 1) == bdg.BDG_EINVAL
 
 

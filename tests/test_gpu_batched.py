@@ -59,8 +59,9 @@ def check_shard(gi, gd, codes, offsets, s, K, rows=None):
 
 
 @pytest.mark.parametrize("bits,K,schedule", [
-    (256, 32, 0), (128, 7, 0), (512, 100, 0), (192, 64, 0),
+    (256, 32, 3), (128, 7, 3), (512, 100, 3), (192, 64, 3),   # lists in LDS
     (256, 32, 2), (128, 7, 2), (512, 100, 2), (512, 128, 2),  # lists in global memory
+    (192, 64, 0), (256, 16, 0),  # the default: LDS at 192 bits, global lists at 256
 ])
 def test_small_and_ragged_shards(bits, K, schedule):
     # empty, single-row, fewer rows than K, tile edges (255/256/257, 383/384/385),
@@ -118,6 +119,8 @@ def test_orders_graph_replay_and_autotune_agree():
         stream.synchronize()
         got = to_np(out)
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), f"replay {rep}"
+    # the default resolves to the global-lists schedule here
+    assert plan.info().schedule == bdg.SCHEDULE_GLOBAL_LISTS
     # the deep-ring schedule builds the same graph, eagerly and through a graph
     plan.set_order(bdg.ORDER_LONGEST_FIRST)
     plan.set_schedule(bdg.SCHEDULE_DEEP_RING)
@@ -133,6 +136,10 @@ def test_orders_graph_replay_and_autotune_agree():
     # lists in global memory: tiles of 384 rows, so fewer work items; the same
     # graph eagerly and through a graph, and back
     items = plan.info().work_items
+    plan.set_schedule(bdg.SCHEDULE_LDS_LISTS)
+    assert plan.info().work_items == items
+    got = to_np(plan.build(d))
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
     plan.set_schedule(bdg.SCHEDULE_GLOBAL_LISTS)
     assert plan.info().work_items == int(np.ceil(sizes / 384).sum()) < items
     got = to_np(plan.build(d))
@@ -165,7 +172,7 @@ def test_orders_graph_replay_and_autotune_agree():
     assert rep["knobs"] == ["order", "schedule", "bound_group"]
     cands = rep["candidates"]
     assert len(cands) == 8  # 2 orders, then the other 2 schedules, then 4 more bound settings
-    assert {c["order"] for c in cands} == {0, 1} and {c["schedule"] for c in cands} == {0, 1, 2}
+    assert {c["order"] for c in cands} == {0, 1} and {c["schedule"] for c in cands} == {1, 2, 3}
     assert {256, bdg.BOUND_OFF, 128, 512, 64} == {c["bound_group"] for c in cands}
     got = to_np(plan.build(d))
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
@@ -291,7 +298,9 @@ def test_autotune_build_keeps_the_graph():
     rep = json.loads(report)
     assert rep["knobs"] == ["path", "col_block", "schedule", "bound_group"]
     cands = rep["candidates"]
-    assert {c["schedule"] for c in cands} == {0, 1, 2} and len(cands) >= 6
+    # matrix-core candidates name the schedule they ran (the vector-ALU one has none: 0)
+    assert {c["schedule"] for c in cands if c["path"] == bdg.PATH_MFMA} == {1, 2, 3}
+    assert len(cands) >= 6
     assert {bdg.BOUND_OFF, bdg.BOUND_GROUP_DEFAULT} <= {c["bound_group"] for c in cands}
     rows = np.arange(0, 20_000, 97)
     # every candidate schedule the tuner timed builds the same graph

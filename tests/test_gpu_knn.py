@@ -75,20 +75,26 @@ GRID = [
 ]
 
 
-@pytest.mark.parametrize("path", [POPC, MFMA], ids=["popc", "mfma"])
+# matrix-core path under the default schedule (lists in global memory where
+# built, else in LDS) and with the lists in LDS everywhere
+PATHS = [(POPC, 0), (MFMA, bdg.SCHEDULE_DEFAULT), (MFMA, bdg.SCHEDULE_LDS_LISTS)]
+PATH_IDS = ["popc", "mfma", "mfma-lds"]
+
+
+@pytest.mark.parametrize("path,schedule", PATHS, ids=PATH_IDS)
 @pytest.mark.parametrize("n,bits,K,nc,p", GRID)
-def test_small_grid(path, n, bits, K, nc, p):
+def test_small_grid(path, schedule, n, bits, K, nc, p):
     codes = datagen.clustered_codes(n, bits, nc, p, seed=n * 7 + bits + K)
     want = oracle.knn_rows(codes, K)
-    assert_same(gpu_knn(codes, K, path), want, f"n={n} bits={bits} K={K}")
+    assert_same(gpu_knn(codes, K, path, schedule=schedule), want, f"n={n} bits={bits} K={K}")
 
 
-@pytest.mark.parametrize("path", [POPC, MFMA], ids=["popc", "mfma"])
+@pytest.mark.parametrize("path,schedule", PATHS, ids=PATH_IDS)
 @pytest.mark.parametrize("col_block,row_block", [(37, 0), (100, 333), (999, 64), (1, 2000)])
-def test_blocking_does_not_change_the_graph(path, col_block, row_block):
+def test_blocking_does_not_change_the_graph(path, schedule, col_block, row_block):
     codes = datagen.clustered_codes(1500 if col_block > 1 else 200, 256, 15, 0.2, seed=21)
     want = oracle.knn_rows(codes, 24)
-    got = gpu_knn(codes, 24, path, col_block=col_block, row_block=row_block)
+    got = gpu_knn(codes, 24, path, col_block=col_block, row_block=row_block, schedule=schedule)
     assert_same(got, want, f"col_block={col_block} row_block={row_block}")
 
 
@@ -101,17 +107,19 @@ def test_golden_cube3(path):
         assert_same(got, (exp_idx, exp_dist), f"cube3 bits={bits}")
 
 
-@pytest.mark.parametrize("path", [POPC, MFMA], ids=["popc", "mfma"])
-def test_tie_heavy_inputs(path):
+@pytest.mark.parametrize("path,schedule", PATHS, ids=PATH_IDS)
+def test_tie_heavy_inputs(path, schedule):
     # all codes identical: every distance 0, neighbours are the smallest indices
     codes = np.tile(datagen.uniform_codes(1, 256, seed=5), (300, 1))
-    assert_same(gpu_knn(codes, 50, path), oracle.knn_rows(codes, 50), "identical")
+    assert_same(gpu_knn(codes, 50, path, schedule=schedule), oracle.knn_rows(codes, 50),
+                "identical")
     # 10-cube: 1024 codes, distances 1..10 with binomial multiplicities
     rows = np.array([[(v >> t) & 1 for t in range(10)] + [0] * 118 for v in range(1024)],
                     dtype=np.uint8)
     codes = datagen.pack_bits(rows)
     for K in (10, 256):
-        assert_same(gpu_knn(codes, K, path), oracle.knn_rows(codes, K), f"cube10 K={K}")
+        assert_same(gpu_knn(codes, K, path, schedule=schedule), oracle.knn_rows(codes, K),
+                    f"cube10 K={K}")
 
 
 def test_paths_agree_and_are_deterministic():
@@ -119,6 +127,8 @@ def test_paths_agree_and_are_deterministic():
     a = gpu_knn(codes, 64, POPC)
     b = gpu_knn(codes, 64, MFMA)
     assert_same(a, b, "popc vs mfma")
+    for sc in (bdg.SCHEDULE_LDS_LISTS, bdg.SCHEDULE_DEEP_RING, bdg.SCHEDULE_GLOBAL_LISTS):
+        assert_same(gpu_knn(codes, 64, MFMA, schedule=sc), a, f"mfma schedule {sc}")
     for cb in (5000, 1024, 333):
         assert_same(gpu_knn(codes, 64, MFMA, col_block=cb), a, f"mfma col_block={cb}")
         assert_same(gpu_knn(codes, 64, POPC, col_block=cb), a, f"popc col_block={cb}")
@@ -144,6 +154,9 @@ def test_admission_bounds_keep_the_graph(n, bits, K, nc, p):
     for group in (bdg.BOUND_OFF, 16, 64, bdg.BOUND_GROUP_DEFAULT, 4096, bdg.BOUND_GROUP_MAX):
         print(f"[bounds] n={n} bits={bits} K={K} group={group}", flush=True)
         assert_same(gpu_knn(codes, K, MFMA, bound_group=group), want, f"group={group}")
+        if group in (64, bdg.BOUND_GROUP_DEFAULT):
+            assert_same(gpu_knn(codes, K, MFMA, bound_group=group,
+                                schedule=bdg.SCHEDULE_LDS_LISTS), want, f"group={group} lds")
         if group == 64:
             # several column blocks: the bound also holds for lists carried across them
             assert_same(gpu_knn(codes, K, MFMA, bound_group=group, col_block=n // 3 + 1), want,
@@ -283,8 +296,9 @@ def test_clustered_1m_256b_k64_every_row():
 
 def test_clustered_4m_512b_k100_sampled():
     """4,000,000 codes of 512 bits from 20,000 centres (flip 0.25), K = 100
-    (lists of 128 keys, row tiles of 192 rows), built as the benchmark times
-    it: one persistent launch over column blocks of 262,144. The vector-ALU
+    (the default schedule: lists kept in the output rows, row tiles of 384
+    rows), built as the benchmark times it: one persistent launch over column
+    blocks of 262,144. The vector-ALU
     path gives the same graph on every row; the oracle checks 4,096 seeded rows
     plus the row-tile and column-block edges and the ends."""
     import torch
@@ -298,7 +312,8 @@ def test_clustered_4m_512b_k100_sampled():
     assert torch.equal(idx, pi) and torch.equal(dist, pd), "matrix-core and vector-ALU graphs differ"
     del pi, pd
     g = np.random.default_rng(100)
-    edges = [0, 1, 191, 192, cb - 1, cb, 2 * cb, n - cb, n - 193, n - 192, n - 1]
+    edges = [0, 1, 191, 192, 383, 384, cb - 1, cb, 2 * cb, n - cb, n - 385, n - 384, n - 193,
+             n - 192, n - 1]
     rows = np.unique(np.concatenate([edges, g.choice(n, 4096, replace=False)])).astype(np.int64)
     sel = torch.from_numpy(rows).cuda()
     got = bdg.to_numpy_graph(idx[sel], dist[sel])
@@ -388,12 +403,14 @@ def test_caller_workspace_and_alloc_failure():
     assert (idx.cpu().numpy() == 5).all()
 
 
+@pytest.mark.parametrize("schedule", [bdg.SCHEDULE_DEFAULT, bdg.SCHEDULE_LDS_LISTS],
+                         ids=["default", "lds"])
 @pytest.mark.parametrize("n,bits,K,col_block", [
-    (1500, 256, 24, 37),    # 6 tiles x 41 column blocks: chains of 41 dependent items
-    (2000, 512, 100, 300),  # tiles of 192 rows, lists of 128 keys
+    (1500, 256, 24, 37),    # 6 tiles (4 of 384 rows) x 41 column blocks: chains of 41 items
+    (2000, 512, 100, 300),  # tiles of 192 (384) rows, lists of 128 keys
     (700, 64, 8, 5000),     # one column block: no item waits
 ])
-def test_sweep_control_words(n, bits, K, col_block):
+def test_sweep_control_words(n, bits, K, col_block, schedule):
     # The matrix-core build is one persistent launch over (row tile, column
     # block) items. Besides the graph, its control words at the end of the
     # workspace show that every item ran once and no dependency wait ran out:
@@ -402,7 +419,7 @@ def test_sweep_control_words(n, bits, K, col_block):
     import torch
     codes = datagen.clustered_codes(n, bits, 12, 0.2, seed=n + bits + K)
     want = oracle.knn_rows(codes, K)
-    o = bdg.make_opts(path=MFMA, col_block=col_block)
+    o = bdg.make_opts(path=MFMA, col_block=col_block, tile_schedule=schedule)
     need = bdg.bdg_build_knn_workspace_size(n, bits, K, o)
     ws = torch.zeros(need, dtype=torch.uint8, device="cuda")
     o.workspace, o.workspace_bytes = ws.data_ptr(), need
@@ -411,7 +428,9 @@ def test_sweep_control_words(n, bits, K, col_block):
     assert bdg.bdg_build_knn_ex(dev(codes), n, bits, K, idx, dist, o, None) == 0
     torch.cuda.synchronize()
     assert_same(bdg.to_numpy_graph(idx, dist), want, f"sweep n={n} col_block={col_block}")
-    rt = 256 if K <= 64 else 192
+    # tiles of 384 rows where the default resolves to the global-lists schedule
+    gl = schedule == bdg.SCHEDULE_DEFAULT and bits in (128, 256, 512) and K <= 128
+    rt = 384 if gl else (256 if K <= 64 else 192)
     ntiles = -(-n // rt)
     ncb = -(-n // col_block)
     off = ((((n + 15) // 16 * 16 + 256) * bits) + 255) // 256 * 256
