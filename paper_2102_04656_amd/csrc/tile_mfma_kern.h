@@ -709,11 +709,11 @@ constexpr int threads_of(int W, int NR) {
 constexpr int stage_groups(int W, int NR) {
   return use_producer(W, NR) ? (W <= 4 ? 4 : 2) : (W <= 5 ? 4 : (W <= 8 ? 2 : 1));
 }
-// Schedules: every one computes the same graph. 0 = pending buffers of 32
-// keys per query; 1 = pending buffers of 16 keys per query, the LDS freed
-// going to a deeper stage ring (more stages in flight, more frequent merges).
-// Schedule 1 is built for codes of 128, 256 and 512 bits.
-constexpr int kSchedules = 2;
+// The LDS-list variants (template SC; every one computes the same graph): SC
+// 0 = pending buffers of 32 keys per query (tile schedule 3); SC 1 = pending
+// buffers of 16 keys per query, the LDS freed going to a deeper stage ring
+// (more stages in flight, more frequent merges; tile schedule 1, built for
+// codes of 128, 256 and 512 bits).
 constexpr int kbuf_of(int SC) { return SC == 1 ? 16 : 32; }
 constexpr bool sched_built(int W, int SC) { return SC == 0 || (W == 2 || W == 4 || W == 8); }
 constexpr size_t state_bytes(int K, int qg, int nw, int kb = 32) {
@@ -974,8 +974,9 @@ inline hipError_t launch_sweep_w(const SweepArgs& a, hipStream_t stream) {
 // registers leave room (codes of up to 256 bits) a ninth wave produces the
 // stages, otherwise the compute waves copy them. Measured on 1M 256-bit codes,
 // K = 64, and 4M 512-bit codes, K = 100: 163.6 -> 136.9 ms and 5.16 -> 4.46 s
-// against schedule 0; two groups per wave: 197.6 ms and 4.97 s; four: spills
-// registers at 512 bits, 161.4 ms without a producer at 256.
+// against the LDS lists of schedule 3; two groups per wave: 197.6 ms and
+// 4.97 s; four: spills registers at 512 bits, 161.4 ms without a producer at
+// 256. Stages of 32 codes in rings of five or six at 512 bits: 4.88 / 4.84 s.
 constexpr int kGlQG = 3, kGlWaves = 8, kGlGroups = 4;
 constexpr bool gl_built(int W) { return W == 2 || W == 4 || W == 8; }
 constexpr bool gl_producer(int W) { return W <= 4; }
