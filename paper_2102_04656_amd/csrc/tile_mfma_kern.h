@@ -479,9 +479,11 @@ __device__ __forceinline__ void tile_body(const v4i* __restrict__ frags,
               a[u][s], bq[gq][s], s == 0 ? v4i{0, 0, 0, 0} : acc[u][gq], 0, 0, 0);
       work(s);
       // without a producer, a fence per layer keeps each operand read after
-      // the products that free its registers; with one, the compiler's own
-      // schedule of the reads was measured faster
-      if constexpr (!PROD) __builtin_amdgcn_sched_barrier(0);
+      // the products that free its registers; with one, or with the lists in
+      // global memory (two waves of 48 rows on a SIMD at 512 bits: 4.36
+      // against 4.43 s), the compiler's own schedule of the reads was
+      // measured faster
+      if constexpr (!PROD && !GL) __builtin_amdgcn_sched_barrier(0);
     }
   };
   auto append_unit = [&](const v4i (&acc)[U][QG], const uint32_t cs) {
