@@ -161,40 +161,49 @@ __global__ __launch_bounds__(256) void propagate_kernel(const uint64_t* __restri
   }
   uint32_t maxd = kth_dist();
 
-  // Second floor: the lists of the first-floor neighbours, two neighbours at
-  // a time (both list chunks, then both chunks' codes, are gathered before
-  // either is filtered, so each pair costs one round of dependent loads).
-  // The second chunk is filtered again after the first one's merge; a filter
-  // with an older, larger K-th distance only admits more, so it stays exact.
+  // Second floor: the lists of the first-floor neighbours, kNb neighbours at
+  // a time (all their list chunks, then all the chunks' codes, are gathered
+  // before any is filtered, so each group costs one round of dependent
+  // loads). A later chunk is filtered again after the earlier ones' merges; a
+  // filter with an older, larger K-th distance only admits more, so it stays
+  // exact.
+  constexpr int kNb = 4;
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
-    for (uint32_t tt = 0; tt < (uint32_t)kPW; tt += 2) {
+    for (uint32_t tt = 0; tt < (uint32_t)kPW; tt += kNb) {
       const uint32_t t = r * kPW + tt;
       if (t >= K) break;
-      const uint32_t ya = __builtin_amdgcn_readlane(yv[r], tt);
-      const uint32_t yb = t + 1 < K ? __builtin_amdgcn_readlane(yv[r], tt + 1) : kAbsent;
-      if (ya == kAbsent && yb == kAbsent) continue;  // wave-uniform
+      uint32_t yn[kNb];
+      bool some = false;
+#pragma unroll
+      for (int i = 0; i < kNb; ++i) {
+        yn[i] = t + i < K ? __builtin_amdgcn_readlane(yv[r], tt + i) : kAbsent;
+        some |= yn[i] != kAbsent;
+      }
+      if (!some) continue;  // wave-uniform
       for (uint32_t c0 = 0; c0 < K; c0 += kPW) {
         const uint32_t p = c0 + lane;
-        const uint32_t za = (ya != kAbsent && p < K) ? in_idx[(size_t)ya * K + p] : kAbsent;
-        const uint32_t zb = (yb != kAbsent && p < K) ? in_idx[(size_t)yb * K + p] : kAbsent;
-        const bool va = za != kAbsent && za < n && za != row;
-        const bool vb = zb != kAbsent && zb < n && zb != row;
-        const uint32_t insa = va ? set_insert(set, za) : 0u;
-        const uint32_t insb = vb ? set_insert(set, zb) : 0u;
-        if (__any(insa == 2u || insb == 2u)) exact_set = false;
-        const bool oka = insa != 0u, okb = insb != 0u;
-        const uint32_t ha = oka ? ham_to(za) : 0xFFFFFFFFu;
-        const uint32_t hb = okb ? ham_to(zb) : 0xFFFFFFFFu;
-        const bool pa = oka && ha <= maxd;
-        if (__any(pa)) {
-          absorb(pa ? (((uint64_t)ha << 32) | za) : kNone64, !exact_set);
-          maxd = kth_dist();
+        uint32_t z[kNb], ins[kNb], h[kNb];
+#pragma unroll
+        for (int i = 0; i < kNb; ++i)
+          z[i] = (yn[i] != kAbsent && p < K) ? in_idx[(size_t)yn[i] * K + p] : kAbsent;
+        bool lost = false;
+#pragma unroll
+        for (int i = 0; i < kNb; ++i) {
+          const bool v = z[i] != kAbsent && z[i] < n && z[i] != row;
+          ins[i] = v ? set_insert(set, z[i]) : 0u;
+          lost |= ins[i] == 2u;
         }
-        const bool pb = okb && hb <= maxd;
-        if (__any(pb)) {
-          absorb(pb ? (((uint64_t)hb << 32) | zb) : kNone64, !exact_set);
-          maxd = kth_dist();
+        if (__any(lost)) exact_set = false;
+#pragma unroll
+        for (int i = 0; i < kNb; ++i) h[i] = ins[i] != 0u ? ham_to(z[i]) : 0xFFFFFFFFu;
+#pragma unroll
+        for (int i = 0; i < kNb; ++i) {
+          const bool pass = ins[i] != 0u && h[i] <= maxd;
+          if (__any(pass)) {
+            absorb(pass ? (((uint64_t)h[i] << 32) | z[i]) : kNone64, !exact_set);
+            maxd = kth_dist();
+          }
         }
       }
     }
