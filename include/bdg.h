@@ -139,7 +139,10 @@ typedef struct bdg_knn_opts {
                                     of LDS, which leaves room for eight
                                     compute waves of 48 rows (each operand
                                     read feeds more products); codes of 128,
-                                    256 or 512 bits with up to 128 keys */
+                                    256 or 512 bits with up to 128 keys.
+                                    Until the build (or the resumed row
+                                    range) completes, out_idx holds these
+                                    intermediate keys */
 #define BDG_SCHEDULE_LDS_LISTS 3 /* lists in LDS, 32 pending keys per row;
                                     every code length and K */
 
